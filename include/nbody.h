@@ -1,0 +1,248 @@
+/*
+ * nbody.h -- C ABI of the MI355X (gfx950) direct N-body hot-path library.
+ *
+ * The library computes the hot path of a direct-summation gravitational
+ * N-body integrator with a 4th-order Hermite predictor/corrector and
+ * individual block time steps, as used by Groen, Portegies Zwart, McMillan &
+ * Makino, "Distributed N-body Simulation on the Grid Using Dedicated
+ * Hardware" (section 2 for the scheme, section 4.1 for the step list, and
+ * section 4.4 for the step list when a force accelerator does the pairwise
+ * sums).  One block step is:
+ *
+ *   select   the next system time t = min_i(t_i + dt_i) and the block of
+ *            n active particles due at t          (section 4.1, step 2)
+ *   predict  positions and velocities of all N particles to t
+ *                                                 (section 4.1, step 3)
+ *   force    acceleration, jerk (and potential) on the n active particles
+ *            from all N particles                 (section 4.1, step 4)
+ *   correct  the n active particles and give each a new block step
+ *                                                 (section 4.1, step 5)
+ *
+ * Units: G = 1.  Softening enters as s = |r|^2 + eps^2.  Block steps are
+ * powers of two between 2^dt_min_log2 and 2^dt_max_log2 (the paper uses
+ * 2^-22 and 2^-3).  Times are kept as integer ticks of 2^dt_min_log2.
+ *
+ * Memory and ownership.  Every pointer named *_dev is a device pointer.  The
+ * caller owns the particle state (nbody_state), all output buffers and the
+ * HIP stream; the library never frees them.  The context owns its internal
+ * buffers: the predicted j-particle buffer, the active list, the work plan,
+ * partial sums, counters, and the captured HIP graph.  All work is enqueued
+ * asynchronously on the caller's stream unless a call returns host values.
+ *
+ * Errors.  Every call returns an int status (NBODY_OK = 0 or a negative
+ * code) and never aborts or throws.  Host-checkable arguments are checked
+ * before anything is enqueued.  Faults found on the device (non-finite
+ * state, index out of range, a corrected particle that was not due) set a
+ * device error word that the next synchronising call (nbody_sync,
+ * nbody_step_block with outputs, nbody_run_until, nbody_get_stats) reports
+ * and clears.
+ *
+ * Threads.  A context is not thread safe: calls on one context must not
+ * overlap.  Distinct contexts are independent.
+ */
+#ifndef NBODY_H
+#define NBODY_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define NBODY_OK 0
+#define NBODY_EINVAL (-1)       /* bad argument (checked on the host)            */
+#define NBODY_ESTATE (-2)       /* call out of order, or a particle not due      */
+#define NBODY_ENOMEM (-3)       /* device allocation failed                      */
+#define NBODY_EDEVICE (-4)      /* HIP runtime error                             */
+#define NBODY_ENONFINITE (-5)   /* the device produced a non-finite value        */
+#define NBODY_EUNSUPPORTED (-6) /* valid but not supported by this build         */
+#define NBODY_ERANGE (-7)       /* the device met a particle index out of range  */
+
+/* arithmetic of the pairwise force sum */
+#define NBODY_PREC_FP64 0  /* every operation in FP64                             */
+#define NBODY_PREC_MIXED 1 /* FP64 coordinates and differences of positions,
+                              FP32 pairwise terms, FP64 accumulation            */
+
+typedef struct nbody_ctx nbody_ctx;
+
+/*
+ * Particle state, structure of arrays, n_total entries per array, device
+ * memory owned by the caller.  pos/vel/mass are inputs to nbody_init; the
+ * library updates pos, vel, acc, jerk, t_tick and level in place as particles
+ * are corrected.  acc/jerk hold the values at the particle's own time t_i.
+ */
+typedef struct {
+    double *pos[3];   /* x, y, z                                            */
+    double *vel[3];   /* vx, vy, vz                                         */
+    double *acc[3];   /* acceleration at t_i                                */
+    double *jerk[3];  /* time derivative of the acceleration at t_i        */
+    double *mass;     /* read only                                          */
+    int64_t *t_tick;  /* t_i = t_tick * 2^dt_min_log2                       */
+    int8_t *level;    /* block step of particle i: dt_i = 2^-level[i]      */
+} nbody_state;
+
+/*
+ * Run parameters.  n_clusters > 1 makes an ensemble of independent systems
+ * that share nothing but the launches: cluster k holds particles
+ * [cluster_offset[k], cluster_offset[k+1]) and has its own clock; one block
+ * step of the ensemble advances every unfinished cluster by its own next
+ * block step.  cluster_offset is a HOST array of n_clusters+1 entries, may be
+ * NULL when n_clusters == 1, and is copied by nbody_create.
+ */
+typedef struct {
+    int64_t n_total;               /* particles in all clusters, 1..2^31-1       */
+    int32_t n_clusters;            /* >= 1                                        */
+    const int64_t *cluster_offset; /* host, n_clusters+1, increasing, 0..n_total */
+    double eps;                    /* softening length, >= 0                      */
+    double eta;                    /* Aarseth step accuracy parameter, > 0        */
+    double eta_init;               /* start-up step parameter (eta_init|a|/|j|)   */
+    int32_t dt_min_log2;           /* smallest step 2^dt_min_log2, >= -40         */
+    int32_t dt_max_log2;           /* largest step, dt_min_log2 <= it <= 0        */
+    int32_t precision;             /* NBODY_PREC_FP64 or NBODY_PREC_MIXED         */
+} nbody_params;
+
+/*
+ * Launch shape of the force kernel (chosen by nbody_autotune or set by
+ * hand).  i_per_lane in {1,2}; j_lanes in {1,4,16,64,256} is the number of
+ * lanes that share one i-particle and split the j loop between them;
+ * j_tile in {128,256} is the number of j-particles staged in LDS per round;
+ * grid is the number of persistent workgroups (0 = library default).
+ */
+typedef struct {
+    int32_t i_per_lane;
+    int32_t j_lanes;
+    int32_t j_tile;
+    int32_t grid;
+} nbody_tuning;
+
+/* Counters accumulated on the device since nbody_init (nbody_get_stats). */
+typedef struct {
+    int64_t block_steps;   /* block steps with n > 0, summed over clusters    */
+    int64_t updates;       /* corrected particles (sum of block sizes)        */
+    double interactions;   /* pairwise force evaluations, n*N summed          */
+    int64_t dt_clamped;    /* steps that wanted less than 2^dt_min_log2       */
+} nbody_stats;
+
+/* Human readable text for a status code; never NULL. */
+const char *nbody_strerror(int status);
+
+/*
+ * Create a context for the given parameters and caller-owned state.
+ * `stream` is a hipStream_t (NULL = the null stream).  Allocates the
+ * context's device buffers (about 120 B per particle plus the work plan).
+ * The state is not read until nbody_init.
+ * Errors: EINVAL (bad sizes, offsets, eps, eta, step range, precision or a
+ * NULL state array), ENOMEM, EDEVICE.
+ */
+int nbody_create(const nbody_params *params, const nbody_state *state, void *stream,
+                 nbody_ctx **out);
+
+/* Release the context's device buffers and graph; caller memory untouched. */
+int nbody_destroy(nbody_ctx *ctx);
+
+/*
+ * Start-up (section 4.1, step 1): set every t_i to 0, compute acceleration
+ * and jerk of every particle from all particles of its cluster (one full
+ * n = N sweep), and give each particle its start-up block step: the largest
+ * power of two not above eta_init |a|/|j|, clamped to the step range.
+ * Resets the counters and the device error word.
+ */
+int nbody_init(nbody_ctx *ctx);
+
+/*
+ * Predict all particles to time t (section 4.1, step 3) into the context's
+ * j-particle buffer:  d = t - t_i,  xp = x + v d + a d^2/2 + jerk d^3/6,
+ * vp = v + a d + jerk d^2/2, in FP64.  t must be a multiple of
+ * 2^dt_min_log2 and not before any particle's t_i (the latter is not
+ * checked).  Single-cluster contexts only (EUNSUPPORTED otherwise).
+ */
+int nbody_predict(nbody_ctx *ctx, double t);
+
+/*
+ * Force, jerk and potential on the n listed particles from all particles
+ * (section 4.1, step 4), at the positions and velocities predicted by the
+ * last nbody_predict, which must have been made at the same t (ESTATE
+ * otherwise):
+ *   a_i    =  sum_{j != i} m_j r s^{-3/2}
+ *   jerk_i =  sum_{j != i} m_j [w s^{-3/2} - 3 (r.w) r s^{-5/2}]
+ *   pot_i  = -sum_{j != i} m_j s^{-1/2}
+ * with r = x_j - x_i, w = v_j - v_i, s = |r|^2 + eps^2.
+ * i_list_dev: int32[n] particle indices, duplicates allowed; an index
+ * outside [0, n_total) makes the next synchronising call return ERANGE (the
+ * slot's outputs are then unspecified).  Outputs are FP64 structure of
+ * arrays: acc_dev[c*n + k] is component c of particle i_list[k];
+ * jerk_dev likewise; pot_dev[k] (pot_dev may be NULL).  1 <= n <= n_total.
+ * Single-cluster contexts only.
+ */
+int nbody_force_jerk(nbody_ctx *ctx, const int32_t *i_list_dev, int64_t n, double t,
+                     double *acc_dev, double *jerk_dev, double *pot_dev);
+
+/*
+ * Hermite corrector (section 4.1, step 5) for the n listed particles, which
+ * must all be due at t (t_i + dt_i = t; otherwise the next synchronising
+ * call returns ESTATE) and must be distinct.  acc_dev/jerk_dev hold the new
+ * acceleration and jerk at t in the layout nbody_force_jerk writes.  Updates
+ * pos, vel, acc, jerk, t_tick and level of those particles:
+ *   a2 = [-6(a0-a1) - dt(4j0+2j1)]/dt^2,  a3 = [12(a0-a1) + 6dt(j0+j1)]/dt^3
+ *   x1 = xp + a2 dt^4/24 + a3 dt^5/120,   v1 = vp + a2 dt^3/6 + a3 dt^4/24
+ * and the next step from Aarseth's criterion with eta,
+ *   dt' = sqrt(eta (|a1||a2'| + |j1|^2) / (|j1||a3| + |a2'|^2)),  a2' = a2 + dt a3,
+ * quantised: halve until dt <= dt' (not below the minimum); double once if
+ * dt' >= 2dt, t is a multiple of 2dt and 2dt is within the maximum.
+ * A non-finite result makes the next synchronising call return ENONFINITE.
+ * Single-cluster contexts only.
+ */
+int nbody_correct(nbody_ctx *ctx, const int32_t *i_list_dev, int64_t n, double t,
+                  const double *acc_dev, const double *jerk_dev);
+
+/*
+ * One block step of every cluster, driven entirely from the device: select,
+ * predict, force, correct.  Nothing is read back unless t_out or n_out is
+ * non-NULL; then the call synchronises and returns the new time of cluster 0
+ * and the block size summed over clusters.
+ */
+int nbody_step_block(nbody_ctx *ctx, double *t_out, int64_t *n_out);
+
+/*
+ * Block steps until no cluster has a next block time <= t_end (section 4.1,
+ * step 6).  Steps are replayed from a captured HIP graph in batches; with
+ * steps of 2^dt_max_log2 or less and t_end a multiple of 2^dt_max_log2,
+ * every particle ends exactly at t_end.  t_end must be a multiple of
+ * 2^dt_min_log2.  Synchronises; *n_steps_out (may be NULL) receives the
+ * number of ensemble block steps that did work.
+ */
+int nbody_run_until(nbody_ctx *ctx, double t_end, int64_t *n_steps_out);
+
+/* Wait for the context's work and report (then clear) the device error word. */
+int nbody_sync(nbody_ctx *ctx);
+
+/* Synchronise and read the counters since nbody_init (the error word too). */
+int nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
+
+/*
+ * Copy the predicted positions and velocities from the last nbody_predict
+ * (or block step) into caller buffers pos_dev[c*n_total + i],
+ * vel_dev[c*n_total + i] in FP64 (mixed contexts keep predicted velocities
+ * in FP32; they are widened).  For checking the predictor.
+ */
+int nbody_read_predicted(nbody_ctx *ctx, double *pos_dev, double *vel_dev);
+
+/* Read / set the force kernel's launch shape (EINVAL for an unsupported shape). */
+int nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
+int nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *tuning);
+
+/*
+ * Time every supported launch shape of the force kernel on the current
+ * state for a block of n_probe particles (1 <= n_probe <= largest cluster,
+ * 0 = each cluster's full size) and keep the fastest.  Predicts to the
+ * current time of cluster 0 first; does not change the particle state.
+ * *best_ms (may be NULL) receives the best time per force call.
+ */
+int nbody_autotune(nbody_ctx *ctx, int64_t n_probe, nbody_tuning *best, double *best_ms);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NBODY_H */

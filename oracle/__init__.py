@@ -167,6 +167,22 @@ class System:
                           float(t0), _p(self.a), _p(self.jk), _p(self.t_i), _p(self.dt_i),
                           ctypes.byref(self.n_clamped))
 
+    @classmethod
+    def from_state(cls, x, v, m, a, jk, t_i, dt_i, prm: Params):
+        """An oracle system holding the given state as is (no start-up sweep)."""
+        self = cls.__new__(cls)
+        self.x = _f64(x).copy()
+        n_total = self.x.shape[0]
+        self.v = _f64(v, (n_total, 3)).copy()
+        self.m = _f64(m, (n_total,)).copy()
+        self.a = _f64(a, (n_total, 3)).copy()
+        self.jk = _f64(jk, (n_total, 3)).copy()
+        self.t_i = _f64(t_i, (n_total,)).copy()
+        self.dt_i = _f64(dt_i, (n_total,)).copy()
+        self.prm = prm
+        self.n_clamped = ctypes.c_int64(0)
+        return self
+
     @property
     def n(self):
         return self.x.shape[0]

@@ -1,0 +1,519 @@
+// Force + jerk (+ potential) on the active block from all particles of its
+// cluster (section 4.1, step 4; the sum GRAPE-6 pipelines evaluate in
+// section 4.4).  For each listed i and every j of i's cluster:
+//   r = x_j - x_i, w = v_j - v_i, s = |r|^2 + eps^2
+//   a_i += m_j r s^{-3/2}
+//   jerk_i += m_j [w s^{-3/2} - 3 (r.w) r s^{-5/2}]
+//   pot_i -= m_j s^{-1/2}
+//
+// Work decomposition.  A persistent grid walks a list of work items built on
+// the device (k_plan): item = (cluster, i-block, j-slice).  Inside a 256-thread
+// workgroup, lane groups of J_LANES consecutive lanes share one i-particle and
+// split each LDS j-tile between them; every lane holds I_PER_LANE i-particles
+// in registers.  j-particles are staged in LDS from coalesced structure-of-
+// arrays loads and read back as broadcasts (J_LANES = 1) or as consecutive
+// addresses (J_LANES > 1).  Lane groups are reduced with cross-lane shuffles,
+// and workgroups of one i-block (j-slices) through partial sums that k_reduce
+// adds in slice order, so every result is bitwise deterministic.
+//
+// Arithmetic.  MIXED: positions are double-single pairs whose hi part lies
+// on a fixed grid (hi = q rint(x/q), lo = fl32(x - hi)), so hi_j - hi_i is
+// exact and r = (x_j^hi - x_i^hi) + (x_j^lo - x_i^lo) has one rounding that
+// does not depend on i's low bits (with hi = fl32(x) that rounding repeats for
+// every far j and shifts i's position systematically).  After r everything is
+// FP32 with the hardware reciprocal square root; per-lane FP32 partial sums
+// are flushed to FP64 accumulators every 128 j.  The jerk is kept as two sums,
+// sum m s^{-3/2} w and sum m s^{-5/2} (r.w) r, combined in FP64 as the first
+// minus three times the second (one multiply less per interaction).
+// Near field: a pair with m_max/s > near_frac*|a_i| (|a_i| from the
+// particle's stored acceleration) can carry a term comparable to the whole
+// force, where FP32 rounding would exceed the error budget; such pairs are
+// masked out of the FP32 sums and evaluated in FP64 in a rarely taken branch.
+// FP64: every operation in double precision; s^{-1/2} from the hardware
+// estimate refined by one third-order Newton step.
+//
+// The self term (j = i) gives r = w = 0 and so adds nothing to a and jerk;
+// its potential contribution m_i eps^{-1} is removed once per i (same
+// arithmetic as in the loop).  With eps = 0 the self term is skipped instead.
+#include <hip/hip_runtime.h>
+
+#include "nbody_internal.h"
+
+namespace nb {
+
+namespace {
+
+// s^{-1/2} in FP64: v_rsq_f64 (about 2^-23 relative) plus one Newton step of
+// third order: y <- y + y e (1/2 + 3/8 e), e = 1 - s y^2.
+__device__ inline double rsqrt_f64(double s) {
+    const double y = __builtin_amdgcn_rsq(s);
+    const double e = fma(-s * y, y, 1.0);
+    return fma(y * e, fma(0.375, e, 0.5), y);
+}
+
+template <int LJ>
+__device__ inline double group_sum(double v) {
+    // butterfly over the LJ consecutive lanes of a group (LJ <= 64)
+#pragma unroll
+    for (int o = LJ / 2; o > 0; o >>= 1)
+        v += __shfl_xor(v, o);
+    return v;
+}
+
+struct Acc64 {
+    double ax, ay, az, jx, jy, jz, p;
+};
+
+template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL>
+__global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
+    static_assert(LJ == 1 || LJ == 4 || LJ == 16 || LJ == 64 || LJ == 256, "J_LANES");
+    static_assert(LJ == 1 || I == 1, "several i per lane only without lane groups");
+    constexpr int NI = kWG / LJ;  // i-slots per workgroup
+    constexpr int IB = NI * I;    // i-particles per work item
+    constexpr int JPL = JT / LJ;  // j per lane per tile
+    static_assert(JT % LJ == 0 && JT % kWG == 0, "tile");
+    // FP32 partial sums are flushed after kFlushJ j per lane
+    constexpr int kFlushJ = 128;
+    constexpr int CHJ = JPL < kFlushJ ? JPL : kFlushJ;   // j per lane per chunk
+    constexpr int NCH = JPL / CHJ;                       // chunks per tile
+    constexpr int FLUSH_TILES = NCH > 1 ? 1 : kFlushJ / JPL;
+
+    __shared__ float4 sP[MIXED ? JT : 1];
+    __shared__ float4 sQ[MIXED ? JT : 1];
+    __shared__ float2 sR[MIXED ? JT : 1];
+    __shared__ double2 sA[MIXED ? 1 : JT];
+    __shared__ double2 sB[MIXED ? 1 : JT];
+    __shared__ double2 sC[MIXED ? 1 : JT];
+    __shared__ double sD[MIXED ? 1 : JT];
+    __shared__ double sRed[LJ == 256 ? 4 * 7 : 1];
+    // per-lane list of near pairs found in the current tile (tile-local j)
+    constexpr int kNearCap = 8;
+    __shared__ uint8_t sNear[MIXED ? I * kNearCap * kWG : 1];
+
+    const int tid = threadIdx.x;
+    int lj, li;
+    if (LJ <= 64) {
+        const int lane = tid & 63, w = tid >> 6;
+        lj = lane % LJ;
+        li = w * (64 / LJ) + lane / LJ;
+    } else {
+        lj = tid;
+        li = 0;
+    }
+
+    __shared__ int64_t s_item;
+    if (uniform_i32(*fa.cls) != fa.my_cls)
+        return;
+    const int64_t total = uniform_i64(*fa.total_items);
+    for (;;) {
+        if (tid == fa.fetch_lane)
+            s_item = (int64_t)atomicAdd(fa.item_counter, 1ull);
+        __syncthreads();
+        const int64_t item = uniform_i64(s_item);
+        __syncthreads();
+        if (item >= total)
+            break;
+        // locate the cluster of this item (largest c with item_begin[c] <= item)
+        int c = 0;
+        if (fa.C > 1) {
+            int lo = 0, hi = fa.C - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (fa.item_begin[mid] <= item)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            c = lo;
+        }
+        c = uniform_i32(c);
+        const int64_t local = item - uniform_i64(fa.item_begin[c]);
+        const int S = uniform_i32(fa.S[c]);
+        const int64_t ib = local / S;
+        const int js = (int)(local - ib * S);
+        const int64_t n_c = uniform_i32(fa.n_cur[c]);
+        const int64_t cb = uniform_i64(fa.off[c]), ce = uniform_i64(fa.off[c + 1]);
+        const int64_t jl = uniform_i32(fa.jlen[c]);
+        const int64_t j0 = cb + (int64_t)js * jl;
+        const int64_t j1 = min(ce, j0 + jl);
+        const int64_t slot0 = fa.slots_at_offsets ? cb : 0;
+
+        // ---- i-particles into registers
+        bool valid[I];
+        int64_t kk[I];
+        int64_t gi[I];
+        float xh[I], yh[I], zh[I], xl[I], yl[I], zl[I], vxi[I], vyi[I], vzi[I], mi[I];
+        float scrit[I];
+        double X[I], Y[I], Z[I], VX[I], VY[I], VZ[I], M[I];
+#pragma unroll
+        for (int ii = 0; ii < I; ii++) {
+            kk[ii] = ib * IB + ii * NI + li;
+            valid[ii] = kk[ii] < n_c;
+            int64_t i = valid[ii] ? (int64_t)fa.i_list[slot0 + kk[ii]] : cb;
+            if (valid[ii] && (i < cb || i >= ce)) {
+                atomicOr(fa.err, kErrRange);
+                i = cb;
+            }
+            gi[ii] = i;
+            if (MIXED) {
+                const float4 p = fa.jb.P[i], q = fa.jb.Q[i];
+                const float2 r = fa.jb.R[i];
+                xh[ii] = p.x; yh[ii] = p.y; zh[ii] = p.z; mi[ii] = p.w;
+                xl[ii] = q.x; yl[ii] = q.y; zl[ii] = q.z; vxi[ii] = q.w;
+                vyi[ii] = r.x; vzi[ii] = r.y;
+                // near-field threshold on s from |a_i| (0 = none)
+                float sc = 0.f;
+                if (fa.near_frac > 0.f) {
+                    const double ha = sqrt(fa.hax[i] * fa.hax[i] + fa.hay[i] * fa.hay[i] +
+                                           fa.haz[i] * fa.haz[i]);
+                    const double v = (double)fa.mmax[c] / ((double)fa.near_frac * ha);
+                    sc = (ha > 0.0 && v < 3.0e38) ? (float)v : 0.f;
+                }
+                scrit[ii] = sc;
+            } else {
+                const double2 a = fa.jb.A[i], b = fa.jb.B[i], cc = fa.jb.C[i];
+                X[ii] = a.x; Y[ii] = a.y; Z[ii] = b.x; M[ii] = b.y;
+                VX[ii] = cc.x; VY[ii] = cc.y; VZ[ii] = fa.jb.D[i];
+            }
+        }
+
+        Acc64 acc[I];
+        float fax[I], fay[I], faz[I], f1x[I], f1y[I], f1z[I], f2x[I], f2y[I], f2z[I], fp[I];
+#pragma unroll
+        for (int ii = 0; ii < I; ii++) {
+            acc[ii] = Acc64{0, 0, 0, 0, 0, 0, 0};
+            fax[ii] = fay[ii] = faz[ii] = 0.f;
+            f1x[ii] = f1y[ii] = f1z[ii] = 0.f;
+            f2x[ii] = f2y[ii] = f2z[ii] = 0.f;
+            fp[ii] = 0.f;
+        }
+        // FP64 form keeps the second jerk sum separately too
+        double d2x[I], d2y[I], d2z[I];
+#pragma unroll
+        for (int ii = 0; ii < I; ii++)
+            d2x[ii] = d2y[ii] = d2z[ii] = 0.0;
+
+        int tcount = 0;
+        for (int64_t tb = j0; tb < j1; tb += JT) {
+            int ncnt[I];
+            float sc_eff[I];
+#pragma unroll
+            for (int ii = 0; ii < I; ii++) {
+                ncnt[ii] = 0;
+                sc_eff[ii] = MIXED ? scrit[ii] : 0.f;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = tid; t < JT; t += kWG) {
+                const int64_t j = tb + t;
+                if (MIXED) {
+                    if (j < j1) {
+                        sP[t] = fa.jb.P[j];
+                        sQ[t] = fa.jb.Q[j];
+                        sR[t] = fa.jb.R[j];
+                    } else {  // massless padding far away: contributes exactly 0
+                        sP[t] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
+                        sQ[t] = make_float4(0.f, 0.f, 0.f, 0.f);
+                        sR[t] = make_float2(0.f, 0.f);
+                    }
+                } else {
+                    if (j < j1) {
+                        sA[t] = fa.jb.A[j];
+                        sB[t] = fa.jb.B[j];
+                        sC[t] = fa.jb.C[j];
+                        sD[t] = fa.jb.D[j];
+                    } else {
+                        sA[t] = make_double2(1e18, 1e18);
+                        sB[t] = make_double2(1e18, 0.0);
+                        sC[t] = make_double2(0.0, 0.0);
+                        sD[t] = 0.0;
+                    }
+                }
+            }
+            __syncthreads();
+
+            if (MIXED) {
+#pragma unroll
+                for (int ch = 0; ch < NCH; ch++) {
+#pragma unroll 4
+                    for (int u = 0; u < CHJ; u++) {
+                        const int t = lj + (ch * CHJ + u) * LJ;
+                        const float4 p = sP[t];
+                        const float4 q = sQ[t];
+                        const float2 r = sR[t];
+#pragma unroll
+                        for (int ii = 0; ii < I; ii++) {
+                            const float dx = (p.x - xh[ii]) + (q.x - xl[ii]);
+                            const float dy = (p.y - yh[ii]) + (q.y - yl[ii]);
+                            const float dz = (p.z - zh[ii]) + (q.z - zl[ii]);
+                            const float wx = q.w - vxi[ii];
+                            const float wy = r.x - vyi[ii];
+                            const float wz = r.y - vzi[ii];
+                            const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, fa.eps2f)));
+                            const float rw = __builtin_fmaf(dz, wz, __builtin_fmaf(dy, wy, dx * wx));
+                            const bool near = s < sc_eff[ii];
+                            float rinv = __builtin_amdgcn_rsqf(s);
+                            if (EXCL)
+                                rinv = s > 0.f ? rinv : 0.f;
+                            rinv = near ? 0.f : rinv;
+                            const float rinv2 = rinv * rinv;
+                            const float mr = p.w * rinv;
+                            const float mr3 = mr * rinv2;
+                            const float al = rw * rinv2;
+                            const float be = mr3 * al;
+                            if (POT)
+                                fp[ii] += mr;
+                            fax[ii] = __builtin_fmaf(mr3, dx, fax[ii]);
+                            fay[ii] = __builtin_fmaf(mr3, dy, fay[ii]);
+                            faz[ii] = __builtin_fmaf(mr3, dz, faz[ii]);
+                            f1x[ii] = __builtin_fmaf(mr3, wx, f1x[ii]);
+                            f1y[ii] = __builtin_fmaf(mr3, wy, f1y[ii]);
+                            f1z[ii] = __builtin_fmaf(mr3, wz, f1z[ii]);
+                            f2x[ii] = __builtin_fmaf(be, dx, f2x[ii]);
+                            f2y[ii] = __builtin_fmaf(be, dy, f2y[ii]);
+                            f2z[ii] = __builtin_fmaf(be, dz, f2z[ii]);
+                            if (near) {
+                                // rare: remember the pair for the FP64 pass below;
+                                // a full list stops masking for the rest of the tile
+                                sNear[(ii * kNearCap + ncnt[ii]) * kWG + tid] = (uint8_t)t;
+                                if (++ncnt[ii] == kNearCap)
+                                    sc_eff[ii] = 0.f;
+                            }
+                        }
+                    }
+                    ++tcount;
+                    if (tcount == FLUSH_TILES || (ch == NCH - 1 && tb + JT >= j1)) {
+                        tcount = 0;
+#pragma unroll
+                        for (int ii = 0; ii < I; ii++) {
+                            acc[ii].ax += (double)fax[ii];
+                            acc[ii].ay += (double)fay[ii];
+                            acc[ii].az += (double)faz[ii];
+                            acc[ii].jx += (double)f1x[ii] - 3.0 * (double)f2x[ii];
+                            acc[ii].jy += (double)f1y[ii] - 3.0 * (double)f2y[ii];
+                            acc[ii].jz += (double)f1z[ii] - 3.0 * (double)f2z[ii];
+                            if (POT)
+                                acc[ii].p += (double)fp[ii];
+                            fax[ii] = fay[ii] = faz[ii] = 0.f;
+                            f1x[ii] = f1y[ii] = f1z[ii] = 0.f;
+                            f2x[ii] = f2y[ii] = f2z[ii] = 0.f;
+                            fp[ii] = 0.f;
+                        }
+                    }
+                }
+                // FP64 pass over the near pairs of this tile (double-single positions,
+                // FP64 masses, FP32 velocities)
+#pragma unroll
+                for (int ii = 0; ii < I; ii++) {
+                    for (int k = 0; k < ncnt[ii]; k++) {
+                        const int t = sNear[(ii * kNearCap + k) * kWG + tid];
+                        const int64_t j = tb + t;
+                        if (j == gi[ii] || j >= j1)
+                            continue;
+                        const float4 p = sP[t];
+                        const float4 q = sQ[t];
+                        const float2 r = sR[t];
+                        const double ex = ((double)p.x - (double)xh[ii]) + ((double)q.x - (double)xl[ii]);
+                        const double ey = ((double)p.y - (double)yh[ii]) + ((double)q.y - (double)yl[ii]);
+                        const double ez = ((double)p.z - (double)zh[ii]) + ((double)q.z - (double)zl[ii]);
+                        const double ux = (double)(q.w - vxi[ii]);
+                        const double uy = (double)(r.x - vyi[ii]);
+                        const double uz = (double)(r.y - vzi[ii]);
+                        const double sd = fma(ez, ez, fma(ey, ey, fma(ex, ex, fa.eps2)));
+                        const double ri = rsqrt_f64(sd);
+                        const double ri2 = ri * ri;
+                        const double m1 = fa.m64[j] * ri;
+                        const double m3 = m1 * ri2;
+                        const double b3 = 3.0 * m3 * (fma(ez, uz, fma(ey, uy, ex * ux)) * ri2);
+                        acc[ii].ax = fma(m3, ex, acc[ii].ax);
+                        acc[ii].ay = fma(m3, ey, acc[ii].ay);
+                        acc[ii].az = fma(m3, ez, acc[ii].az);
+                        acc[ii].jx += m3 * ux - b3 * ex;
+                        acc[ii].jy += m3 * uy - b3 * ey;
+                        acc[ii].jz += m3 * uz - b3 * ez;
+                        if (POT)
+                            acc[ii].p += m1;
+                    }
+                }
+            } else {
+#pragma unroll 2
+                for (int t = lj; t < JT; t += LJ) {
+                    const double2 a = sA[t];
+                    const double2 b = sB[t];
+                    const double2 cv = sC[t];
+                    const double vz = sD[t];
+#pragma unroll
+                    for (int ii = 0; ii < I; ii++) {
+                        const double dx = a.x - X[ii];
+                        const double dy = a.y - Y[ii];
+                        const double dz = b.x - Z[ii];
+                        const double wx = cv.x - VX[ii];
+                        const double wy = cv.y - VY[ii];
+                        const double wz = vz - VZ[ii];
+                        const double s = fma(dz, dz, fma(dy, dy, fma(dx, dx, fa.eps2)));
+                        const double rw = fma(dz, wz, fma(dy, wy, dx * wx));
+                        double rinv = rsqrt_f64(s);
+                        if (EXCL)
+                            rinv = s > 0.0 ? rinv : 0.0;
+                        const double rinv2 = rinv * rinv;
+                        const double mr = b.y * rinv;
+                        const double mr3 = mr * rinv2;
+                        const double be = mr3 * (rw * rinv2);
+                        if (POT)
+                            acc[ii].p += mr;
+                        acc[ii].ax = fma(mr3, dx, acc[ii].ax);
+                        acc[ii].ay = fma(mr3, dy, acc[ii].ay);
+                        acc[ii].az = fma(mr3, dz, acc[ii].az);
+                        acc[ii].jx = fma(mr3, wx, acc[ii].jx);
+                        acc[ii].jy = fma(mr3, wy, acc[ii].jy);
+                        acc[ii].jz = fma(mr3, wz, acc[ii].jz);
+                        d2x[ii] = fma(be, dx, d2x[ii]);
+                        d2y[ii] = fma(be, dy, d2y[ii]);
+                        d2z[ii] = fma(be, dz, d2z[ii]);
+                    }
+                }
+            }
+        }
+        if (!MIXED) {
+#pragma unroll
+            for (int ii = 0; ii < I; ii++) {
+                acc[ii].jx -= 3.0 * d2x[ii];
+                acc[ii].jy -= 3.0 * d2y[ii];
+                acc[ii].jz -= 3.0 * d2z[ii];
+            }
+        }
+
+        // ---- reduce the lane group (J_LANES > 1)
+        bool writer = true;
+        if (LJ > 1 && LJ <= 64) {
+            acc[0].ax = group_sum<LJ>(acc[0].ax);
+            acc[0].ay = group_sum<LJ>(acc[0].ay);
+            acc[0].az = group_sum<LJ>(acc[0].az);
+            acc[0].jx = group_sum<LJ>(acc[0].jx);
+            acc[0].jy = group_sum<LJ>(acc[0].jy);
+            acc[0].jz = group_sum<LJ>(acc[0].jz);
+            if (POT)
+                acc[0].p = group_sum<LJ>(acc[0].p);
+            writer = lj == 0;
+        } else if (LJ == 256) {
+            double v[7] = {acc[0].ax, acc[0].ay, acc[0].az, acc[0].jx, acc[0].jy, acc[0].jz, acc[0].p};
+#pragma unroll
+            for (int q = 0; q < 7; q++)
+                v[q] = group_sum<64>(v[q]);
+            __syncthreads();
+            if ((tid & 63) == 0) {
+#pragma unroll
+                for (int q = 0; q < 7; q++)
+                    sRed[(tid >> 6) * 7 + q] = v[q];
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double r[7];
+#pragma unroll
+                for (int q = 0; q < 7; q++)
+                    r[q] = ((sRed[q] + sRed[7 + q]) + sRed[14 + q]) + sRed[21 + q];
+                acc[0] = Acc64{r[0], r[1], r[2], r[3], r[4], r[5], r[6]};
+            }
+            writer = tid == 0;
+        }
+
+        // ---- write results or partial sums
+        if (writer) {
+#pragma unroll
+            for (int ii = 0; ii < I; ii++) {
+                if (!valid[ii])
+                    continue;
+                double pot = -acc[ii].p;
+                if (POT && !EXCL && js == 0) {
+                    // remove the self term m_i eps^{-1}, evaluated as in the loop
+                    // (in the mixed form only if the FP32 loop did not mask it)
+                    if (MIXED) {
+                        if (!(fa.eps2f < scrit[ii]))
+                            pot += (double)(mi[ii] * __builtin_amdgcn_rsqf(fa.eps2f));
+                    } else {
+                        pot += M[ii] * rsqrt_f64(fa.eps2);
+                    }
+                }
+                if (S == 1) {
+                    const int64_t o = slot0 + kk[ii];
+                    const int64_t st = fa.out_stride;
+                    fa.out_acc[o] = acc[ii].ax;
+                    fa.out_acc[st + o] = acc[ii].ay;
+                    fa.out_acc[2 * st + o] = acc[ii].az;
+                    fa.out_jerk[o] = acc[ii].jx;
+                    fa.out_jerk[st + o] = acc[ii].jy;
+                    fa.out_jerk[2 * st + o] = acc[ii].jz;
+                    if (POT)
+                        fa.out_pot[o] = pot;
+                } else {
+                    const int64_t o = fa.part_begin[c] + (int64_t)js * n_c + kk[ii];
+                    const int64_t cap = fa.part_cap;
+                    fa.part[o] = acc[ii].ax;
+                    fa.part[cap + o] = acc[ii].ay;
+                    fa.part[2 * cap + o] = acc[ii].az;
+                    fa.part[3 * cap + o] = acc[ii].jx;
+                    fa.part[4 * cap + o] = acc[ii].jy;
+                    fa.part[5 * cap + o] = acc[ii].jz;
+                    fa.part[6 * cap + o] = POT ? pot : 0.0;
+                }
+            }
+        }
+    }
+}
+
+using KernelFn = void (*)(ForceArgs);
+
+template <int I, int LJ, int JT>
+KernelFn pick(int mixed, int pot, int excl) {
+    const int key = mixed * 4 + pot * 2 + excl;
+    switch (key) {
+        case 0: return k_force<I, LJ, JT, false, false, false>;
+        case 1: return k_force<I, LJ, JT, false, false, true>;
+        case 2: return k_force<I, LJ, JT, false, true, false>;
+        case 3: return k_force<I, LJ, JT, false, true, true>;
+        case 4: return k_force<I, LJ, JT, true, false, false>;
+        case 5: return k_force<I, LJ, JT, true, false, true>;
+        case 6: return k_force<I, LJ, JT, true, true, false>;
+        default: return k_force<I, LJ, JT, true, true, true>;
+    }
+}
+
+KernelFn lookup(const Shape &sh, int mixed, int pot, int excl) {
+    if (sh.j_tile != 256)
+        return nullptr;
+    if (sh.j_lanes == 1 && sh.i_per_lane == 1) return pick<1, 1, 256>(mixed, pot, excl);
+    if (sh.j_lanes == 1 && sh.i_per_lane == 2) return pick<2, 1, 256>(mixed, pot, excl);
+    if (sh.i_per_lane != 1) return nullptr;
+    if (sh.j_lanes == 4) return pick<1, 4, 256>(mixed, pot, excl);
+    if (sh.j_lanes == 16) return pick<1, 16, 256>(mixed, pot, excl);
+    if (sh.j_lanes == 64) return pick<1, 64, 256>(mixed, pot, excl);
+    if (sh.j_lanes == 256) return pick<1, 256, 256>(mixed, pot, excl);
+    return nullptr;
+}
+
+}  // namespace
+
+bool force_shape_supported(const Shape &sh) { return lookup(sh, 1, 0, 0) != nullptr; }
+
+int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self) {
+    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self);
+    if (!fn)
+        return 0;
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, reinterpret_cast<const void *>(fn),
+                                                     kWG, 0) != hipSuccess)
+        return 0;
+    return blocks;
+}
+
+hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self,
+                        const ForceArgs &fa, int grid, hipStream_t s) {
+    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self);
+    if (!fn)
+        return hipErrorInvalidValue;
+    ForceArgs a = fa;
+    void *args[] = {&a};
+    return hipLaunchKernel(reinterpret_cast<const void *>(fn), dim3(grid), dim3(kWG), args, 0, s);
+}
+
+}  // namespace nb

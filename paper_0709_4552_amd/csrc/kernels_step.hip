@@ -1,0 +1,650 @@
+// Block-step kernels: selection, work planning, prediction, j-split
+// reduction, Hermite correction and start-up.  All FP64 except the mixed
+// j-particle buffer written by the predictor.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+
+#include "nbody_internal.h"
+
+namespace nb {
+
+namespace {
+
+__device__ inline bool finite3(double a, double b, double c) {
+    return isfinite(a) && isfinite(b) && isfinite(c);
+}
+
+__device__ inline double norm3(double a, double b, double c) {
+    return sqrt(a * a + b * b + c * c);
+}
+
+__device__ inline int64_t dt_ticks(int lev_max, int lev) {
+    return (int64_t)1 << (lev_max - lev);
+}
+
+// ---------------------------------------------------------------- fills
+__global__ void k_fill_i64(int64_t *p, int64_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_i32(int32_t *p, int32_t v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_fill_f64(double *p, double v, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+__global__ void k_iota_i32(int32_t *p, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = (int32_t)i;
+}
+
+// ---------------------------------------------------------------- predictor
+// Third-order Taylor prediction of every particle to its cluster's time
+// (section 4.1, step 3), written to the j-particle buffer.
+template <int MIXED>
+__global__ __launch_bounds__(kWG) void k_predict(State st, Params pr, JBuf jb, const int32_t *cid,
+                                                  const int64_t *t_cur, const int32_t *n_cur,
+                                                  int64_t t_host, int use_host_t) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pr.n_total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        int64_t T = t_host;
+        if (!use_host_t) {
+            const int c = pr.C > 1 ? cid[i] : 0;
+            if (n_cur[c] == 0)
+                continue;
+            T = t_cur[c];
+        }
+        const double d = (double)(T - st.tick[i]) * pr.tick;
+        const double h = 0.5 * d, s6 = d * (1.0 / 6.0);
+        const double ax = st.ax[i], ay = st.ay[i], az = st.az[i];
+        const double jx = st.jx[i], jy = st.jy[i], jz = st.jz[i];
+        const double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
+        // xp = x + d (v + d (a/2 + d j/6)),  vp = v + d (a + d j/2)
+        const double xp = fma(d, fma(d, fma(s6, jx, 0.5 * ax), vx), st.x[i]);
+        const double yp = fma(d, fma(d, fma(s6, jy, 0.5 * ay), vy), st.y[i]);
+        const double zp = fma(d, fma(d, fma(s6, jz, 0.5 * az), vz), st.z[i]);
+        const double vxp = fma(d, fma(h, jx, ax), vx);
+        const double vyp = fma(d, fma(h, jy, ay), vy);
+        const double vzp = fma(d, fma(h, jz, az), vz);
+        const double m = st.m[i];
+        if (MIXED) {
+            // hi on a fixed grid: differences of hi parts are exact, so the
+            // rounding of x_j - x_i does not depend on i's low bits
+            const float xh = (float)(rint(xp * pr.grid_inv) * pr.grid_q);
+            const float yh = (float)(rint(yp * pr.grid_inv) * pr.grid_q);
+            const float zh = (float)(rint(zp * pr.grid_inv) * pr.grid_q);
+            const float xl = (float)(xp - (double)xh);
+            const float yl = (float)(yp - (double)yh);
+            const float zl = (float)(zp - (double)zh);
+            jb.P[i] = make_float4(xh, yh, zh, (float)m);
+            jb.Q[i] = make_float4(xl, yl, zl, (float)vxp);
+            jb.R[i] = make_float2((float)vyp, (float)vzp);
+        } else {
+            jb.A[i] = make_double2(xp, yp);
+            jb.B[i] = make_double2(zp, m);
+            jb.C[i] = make_double2(vxp, vyp);
+            jb.D[i] = vzp;
+        }
+    }
+}
+
+__global__ void k_read_predicted(Params pr, JBuf jb, double *pos, double *vel, int mixed) {
+    const int64_t n = pr.n_total;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        if (mixed) {
+            const float4 p = jb.P[i], q = jb.Q[i];
+            const float2 r = jb.R[i];
+            pos[i] = (double)p.x + (double)q.x;
+            pos[n + i] = (double)p.y + (double)q.y;
+            pos[2 * n + i] = (double)p.z + (double)q.z;
+            vel[i] = q.w;
+            vel[n + i] = r.x;
+            vel[2 * n + i] = r.y;
+        } else {
+            const double2 a = jb.A[i], b = jb.B[i], c = jb.C[i];
+            pos[i] = a.x;
+            pos[n + i] = a.y;
+            pos[2 * n + i] = b.x;
+            vel[i] = c.x;
+            vel[n + i] = c.y;
+            vel[2 * n + i] = jb.D[i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------- selection
+// Section 4.1, step 2: next time of each cluster = min_i (t_i + dt_i), then
+// the block of particles due at that time.  One workgroup per chunk of at
+// most kChunk particles of one cluster.
+__global__ __launch_bounds__(kWG) void k_select_min(State st, Params pr, const int64_t *off,
+                                                    const int32_t *chunk_c,
+                                                    const int64_t *chunk_b, int64_t *t_next) {
+    __shared__ unsigned long long red[kWG / 64];
+    const int64_t k = blockIdx.x;
+    const int c = uniform_i32(chunk_c[k]);
+    const int64_t b = uniform_i64(chunk_b[k]);
+    const int64_t e = min(uniform_i64(off[c + 1]), b + kChunk);
+    unsigned long long best = ULLONG_MAX;
+    for (int64_t i = b + threadIdx.x; i < e; i += kWG) {
+        const unsigned long long nt = (unsigned long long)(st.tick[i] + dt_ticks(pr.lev_max, st.lev[i]));
+        best = nt < best ? nt : best;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long v = __shfl_xor(best, o);
+        best = v < best ? v : best;
+    }
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < kWG / 64; w++)
+            best = red[w] < best ? red[w] : best;
+        atomicMin((unsigned long long *)&t_next[c], best);
+    }
+}
+
+__global__ __launch_bounds__(kWG) void k_select_compact(State st, Params pr, const int64_t *off,
+                                                        const int32_t *chunk_c,
+                                                        const int64_t *chunk_b,
+                                                        const int64_t *t_next, int32_t *n_act,
+                                                        int32_t *i_list, const DevCtl *ctl) {
+    __shared__ int32_t wcount[kWG / 64];
+    __shared__ int32_t base_s;
+    const int64_t k = blockIdx.x;
+    const int c = uniform_i32(chunk_c[k]);
+    const int64_t T = uniform_i64(t_next[c]);
+    if (T > uniform_i64(ctl->t_end_tick))
+        return;
+    const int64_t cb = uniform_i64(off[c]);
+    const int64_t b = uniform_i64(chunk_b[k]);
+    const int64_t e = min(uniform_i64(off[c + 1]), b + kChunk);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    for (int64_t base = b; base < e; base += kWG) {
+        const int64_t i = base + threadIdx.x;
+        const bool due = i < e && st.tick[i] + dt_ticks(pr.lev_max, st.lev[i]) == T;
+        const unsigned long long bal = __ballot(due);
+        const int before = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wcount[w] = __popcll(bal);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int tot = 0;
+            for (int q = 0; q < kWG / 64; q++) {
+                const int cnt = wcount[q];
+                wcount[q] = tot;
+                tot += cnt;
+            }
+            base_s = tot ? atomicAdd(&n_act[c], tot) : 0;
+        }
+        __syncthreads();
+        if (due)
+            i_list[cb + base_s + wcount[w] + before] = (int32_t)i;
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- planning
+// Builds the work list of one force evaluation: cluster c gets
+// ceil(n_c / ib) i-blocks times S_c j-slices.  The shape class (and so ib)
+// follows the mean block size of the active clusters.  One cluster: S is the
+// value in [1, 64] that minimises the modelled time ceil(items/grid) *
+// (tiles per slice + 1).  Several clusters: S_c follows the cluster's share
+// of the work so the whole evaluation has about 4*grid items; the force
+// kernel's work queue balances the rest.  One workgroup.
+__device__ int64_t block_exclusive_scan(int64_t v, int64_t *tmp, int64_t *total) {
+    const int t = threadIdx.x;
+    tmp[t] = v;
+    __syncthreads();
+    for (int o = 1; o < kPlanThreads; o <<= 1) {
+        const int64_t add = t >= o ? tmp[t - o] : 0;
+        __syncthreads();
+        tmp[t] += add;
+        __syncthreads();
+    }
+    const int64_t incl = tmp[t];
+    *total = tmp[kPlanThreads - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t *off, PlanDev pl,
+                                                       int32_t *n_act, int64_t *t_next,
+                                                       DevCtl *ctl, int64_t part_cap,
+                                                       ClassTable ct, int32_t j_tile,
+                                                       int32_t host_n, int64_t host_t,
+                                                       int32_t count_stats) {
+    __shared__ int64_t tmp[kPlanThreads];
+    __shared__ double dred[kPlanThreads];
+    __shared__ int64_t carry_items, carry_parts;
+    __shared__ int s_fallback;
+    __shared__ int s_best_S;
+    const int t = threadIdx.x;
+    const int C = pr.C;
+    // pass 1: take the block sizes of this step; total work
+    double w_local = 0.0;
+    int64_t n_local = 0, act_local = 0;
+    for (int c = t; c < C; c += kPlanThreads) {
+        int32_t n;
+        if (host_n >= 0) {
+            n = host_n;
+            pl.t_cur[c] = host_t;
+        } else {
+            n = n_act[c];
+            pl.t_cur[c] = t_next[c];
+            n_act[c] = 0;
+            t_next[c] = LLONG_MAX;
+        }
+        pl.n_cur[c] = n;
+        const double nc = (double)(off[c + 1] - off[c]);
+        w_local += (double)n * nc;
+        n_local += n;
+        act_local += n > 0;
+    }
+    dred[t] = w_local;
+    tmp[t] = n_local;
+    __syncthreads();
+    for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
+        if (t < o) {
+            dred[t] += dred[t + o];
+            tmp[t] += tmp[t + o];
+        }
+        __syncthreads();
+    }
+    const double W = dred[0];
+    const int64_t n_sum = tmp[0];
+    __syncthreads();
+    tmp[t] = act_local;
+    __syncthreads();
+    for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
+        if (t < o)
+            tmp[t] += tmp[t + o];
+        __syncthreads();
+    }
+    const int64_t n_active_clusters = tmp[0];
+    __syncthreads();
+    // shape class from the mean block size
+    const int64_t n_mean = n_active_clusters > 0 ? n_sum / n_active_clusters : 0;
+    int cls = kClasses - 1;
+    for (int k = 0; k < kClasses; k++)
+        if (n_mean >= ct.min_n[k]) {
+            cls = k;
+            break;
+        }
+    const int64_t ib_size = ct.ib[cls];
+    const int64_t grid = ct.grid[cls];
+    // one cluster: choose S by the cost model
+    if (C == 1) {
+        __shared__ int64_t cost[64];
+        if (t < 64) {
+            const int64_t n = pl.n_cur[0];
+            const int64_t Nc = off[1] - off[0];
+            const int64_t tiles = (Nc + j_tile - 1) / j_tile;
+            const int64_t nib = (n + ib_size - 1) / ib_size;
+            const int64_t S = t + 1;
+            int64_t cst = INT64_MAX;
+            if (S <= tiles && (S == 1 || S * n <= part_cap) && n > 0) {
+                const int64_t tps = (tiles + S - 1) / S;
+                const int64_t Seff = (tiles + tps - 1) / tps;
+                const int64_t waves = (nib * Seff + grid - 1) / grid;
+                cst = waves * (tps + 1);
+            }
+            cost[t] = cst;
+        }
+        __syncthreads();
+        if (t == 0) {
+            int best = 0;
+            for (int q = 1; q < 64; q++)
+                if (cost[q] < cost[best])
+                    best = q;
+            s_best_S = best + 1;
+        }
+        __syncthreads();
+    }
+    if (t == 0)
+        s_fallback = 0;
+    __syncthreads();
+    // pass 2 (repeated once with S = 1 if the partial-sum buffer would overflow)
+    for (int attempt = 0; attempt < 2; attempt++) {
+        if (t == 0) {
+            carry_items = 0;
+            carry_parts = 0;
+        }
+        __syncthreads();
+        for (int c0 = 0; c0 < C; c0 += kPlanThreads) {
+            const int c = c0 + t;
+            int64_t items = 0, parts = 0;
+            int32_t S = 0, jl = 0;
+            if (c < C) {
+                const int64_t n = pl.n_cur[c];
+                const int64_t Nc = off[c + 1] - off[c];
+                if (n > 0 && Nc > 0) {
+                    const int64_t nib = (n + ib_size - 1) / ib_size;
+                    const int64_t tiles = (Nc + j_tile - 1) / j_tile;
+                    int64_t s = 1;
+                    if (!uniform_i32(s_fallback)) {
+                        if (C == 1) {
+                            s = uniform_i32(s_best_S);
+                        } else if (W > 0.0) {
+                            const double share = (double)n * (double)Nc / W;
+                            s = (int64_t)ceil(4.0 * (double)grid * share / (double)nib);
+                        }
+                        s = s < 1 ? 1 : (s > tiles ? tiles : s);
+                    }
+                    const int64_t tiles_per = (tiles + s - 1) / s;
+                    jl = (int32_t)(tiles_per * j_tile);
+                    S = (int32_t)((Nc + jl - 1) / jl);
+                    items = nib * S;
+                    parts = S > 1 ? (int64_t)S * n : 0;
+                }
+                pl.S[c] = S;
+                pl.jlen[c] = jl;
+            }
+            int64_t tot_i, tot_p;
+            const int64_t ex_i = block_exclusive_scan(items, tmp, &tot_i);
+            const int64_t ex_p = block_exclusive_scan(parts, tmp, &tot_p);
+            if (c < C) {
+                pl.item_begin[c] = carry_items + ex_i;
+                pl.part_begin[c] = carry_parts + ex_p;
+            }
+            __syncthreads();
+            if (t == 0) {
+                carry_items += tot_i;
+                carry_parts += tot_p;
+            }
+            __syncthreads();
+        }
+        if (uniform_i64(carry_parts) <= part_cap)
+            break;
+        __syncthreads();
+        if (t == 0)
+            s_fallback = 1;
+        __syncthreads();
+    }
+    if (t == 0) {
+        pl.item_begin[C] = carry_items;
+        ctl->total_items = carry_items;
+        ctl->part_used = carry_parts;
+        ctl->item_counter = 0;
+        ctl->cls = cls;
+        ctl->n_last = (int32_t)n_sum;
+        ctl->any_active = n_sum > 0;
+        if (carry_parts > part_cap)
+            ctl->err |= kErrPlan;
+        if (count_stats) {
+            ctl->steps += (unsigned long long)n_active_clusters;
+            ctl->updates += (unsigned long long)n_sum;
+            ctl->interactions += W;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- reduction
+// Sums the per-slice partial results in slice order (deterministic).
+__global__ __launch_bounds__(kWG) void k_reduce(ForceArgs fa, const int32_t *cid,
+                                                int64_t slot_space) {
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < slot_space;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int c = fa.C > 1 ? cid[s] : 0;
+        const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
+        const int64_t n = fa.n_cur[c];
+        const int S = fa.S[c];
+        if (k >= n || S <= 1)
+            continue;
+        const int64_t base = fa.part_begin[c] + k;
+        double acc[7];
+#pragma unroll
+        for (int q = 0; q < 7; q++) {
+            double sum = 0.0;
+            for (int js = 0; js < S; js++)
+                sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+            acc[q] = sum;
+        }
+        fa.out_acc[s] = acc[0];
+        fa.out_acc[fa.out_stride + s] = acc[1];
+        fa.out_acc[2 * fa.out_stride + s] = acc[2];
+        fa.out_jerk[s] = acc[3];
+        fa.out_jerk[fa.out_stride + s] = acc[4];
+        fa.out_jerk[2 * fa.out_stride + s] = acc[5];
+        if (fa.out_pot)
+            fa.out_pot[s] = acc[6];
+    }
+}
+
+// ---------------------------------------------------------------- corrector
+// Section 4.1, step 5: Hermite correction of the block and its new steps.
+__global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int32_t *i_list,
+                                                 int32_t slots_at_offsets, const int64_t *off,
+                                                 const int32_t *cid, const int32_t *n_cur,
+                                                 const int64_t *t_cur, int64_t slot_space,
+                                                 const double *an, const double *jn,
+                                                 int64_t in_stride, DevCtl *ctl) {
+    unsigned long long clamps = 0;
+    int32_t err = 0;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < slot_space;
+         s += (int64_t)gridDim.x * blockDim.x) {
+        const int c = pr.C > 1 ? cid[s] : 0;
+        const int64_t cb = off[c];
+        const int64_t k = slots_at_offsets ? s - cb : s;
+        if (k >= n_cur[c])
+            continue;
+        const int64_t i = i_list[s];
+        if (i < cb || i >= off[c + 1]) {
+            err |= kErrRange;
+            continue;
+        }
+        const int64_t T = t_cur[c];
+        const int lev = st.lev[i];
+        const int64_t dtk = dt_ticks(pr.lev_max, lev);
+        if (st.tick[i] + dtk != T) {
+            err |= kErrNotDue;
+            continue;
+        }
+        const double dt = ldexp(1.0, -lev);
+        const double h = 0.5 * dt, s6 = dt * (1.0 / 6.0);
+        const double x0[3] = {st.x[i], st.y[i], st.z[i]};
+        const double v0[3] = {st.vx[i], st.vy[i], st.vz[i]};
+        const double a0[3] = {st.ax[i], st.ay[i], st.az[i]};
+        const double j0[3] = {st.jx[i], st.jy[i], st.jz[i]};
+        double a1[3], j1[3], x1[3], v1[3], a2e[3], a3[3];
+        const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+        const double idt2 = 1.0 / dt2, idt3 = 1.0 / dt3;  // exact: powers of two
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            a1[q] = an[q * in_stride + s];
+            j1[q] = jn[q * in_stride + s];
+            const double xp = fma(dt, fma(dt, fma(s6, j0[q], 0.5 * a0[q]), v0[q]), x0[q]);
+            const double vp = fma(dt, fma(h, j0[q], a0[q]), v0[q]);
+            const double da = a0[q] - a1[q];
+            const double a2 = (-6.0 * da - dt * (4.0 * j0[q] + 2.0 * j1[q])) * idt2;
+            const double a3q = (12.0 * da + 6.0 * dt * (j0[q] + j1[q])) * idt3;
+            x1[q] = xp + a2 * dt4 / 24.0 + a3q * dt5 / 120.0;
+            v1[q] = vp + a2 * dt3 / 6.0 + a3q * dt4 / 24.0;
+            a2e[q] = a2 + dt * a3q;
+            a3[q] = a3q;
+        }
+        ok = finite3(x1[0], x1[1], x1[2]) && finite3(v1[0], v1[1], v1[2]) &&
+             finite3(a1[0], a1[1], a1[2]) && finite3(j1[0], j1[1], j1[2]);
+        if (!ok)
+            err |= kErrNonFinite;
+        // Aarseth criterion and block quantisation
+        const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
+        const double na2 = norm3(a2e[0], a2e[1], a2e[2]), na3 = norm3(a3[0], a3[1], a3[2]);
+        const double num = na * na2 + nj * nj;
+        const double den = nj * na3 + na2 * na2;
+        const double dt_raw = den > 0.0 ? sqrt(pr.eta * num / den) : INFINITY;
+        int nlev = lev;
+        if (dt_raw < dt) {
+            while (nlev < pr.lev_max && ldexp(1.0, -nlev) > dt_raw)
+                nlev++;
+            if (ldexp(1.0, -nlev) > dt_raw)
+                clamps++;
+        } else if (dt_raw >= 2.0 * dt && lev > pr.lev_min && (T % (2 * dtk)) == 0) {
+            nlev = lev - 1;
+        }
+        st.x[i] = x1[0];
+        st.y[i] = x1[1];
+        st.z[i] = x1[2];
+        st.vx[i] = v1[0];
+        st.vy[i] = v1[1];
+        st.vz[i] = v1[2];
+        st.ax[i] = a1[0];
+        st.ay[i] = a1[1];
+        st.az[i] = a1[2];
+        st.jx[i] = j1[0];
+        st.jy[i] = j1[1];
+        st.jz[i] = j1[2];
+        st.tick[i] = T;
+        st.lev[i] = (int8_t)nlev;
+    }
+    if (err)
+        atomicOr(&ctl->err, err);
+    if (clamps)
+        atomicAdd(&ctl->clamps, clamps);
+}
+
+// Start-up: store the first force sweep, t_i = 0 and the start-up step.
+__global__ __launch_bounds__(kWG) void k_init_finish(State st, Params pr, const double *an,
+                                                     const double *jn, int64_t stride,
+                                                     DevCtl *ctl) {
+    unsigned long long clamps = 0;
+    int32_t err = 0;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pr.n_total;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double ax = an[i], ay = an[stride + i], az = an[2 * stride + i];
+        const double jx = jn[i], jy = jn[stride + i], jz = jn[2 * stride + i];
+        if (!finite3(ax, ay, az) || !finite3(jx, jy, jz) || !finite3(st.x[i], st.y[i], st.z[i]) ||
+            !finite3(st.vx[i], st.vy[i], st.vz[i]))
+            err |= kErrNonFinite;
+        const double na = norm3(ax, ay, az), nj = norm3(jx, jy, jz);
+        const double want = nj > 0.0 ? pr.eta_init * na / nj : INFINITY;
+        int lev = pr.lev_min;
+        while (lev < pr.lev_max && ldexp(1.0, -lev) > want)
+            lev++;
+        if (ldexp(1.0, -lev) > want)
+            clamps++;
+        st.ax[i] = ax;
+        st.ay[i] = ay;
+        st.az[i] = az;
+        st.jx[i] = jx;
+        st.jy[i] = jy;
+        st.jz[i] = jz;
+        st.tick[i] = 0;
+        st.lev[i] = (int8_t)lev;
+    }
+    if (err)
+        atomicOr(&ctl->err, err);
+    if (clamps)
+        atomicAdd(&ctl->clamps, clamps);
+}
+
+int grid_for(int64_t n) {
+    int64_t g = (n + kWG - 1) / kWG;
+    if (g < 1)
+        g = 1;
+    if (g > 4096)
+        g = 4096;
+    return (int)g;
+}
+
+}  // namespace
+
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n)), dim3(kWG), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i32, dim3(grid_for(n)), dim3(kWG), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(n)), dim3(kWG), 0, s, p, v, n);
+    return hipGetLastError();
+}
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(k_iota_i32, dim3(grid_for(n)), dim3(kWG), 0, s, p, n);
+    return hipGetLastError();
+}
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_i64, dim3(1), dim3(64), 0, s, p, v, (int64_t)1);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict(const State &st, const Params &pr, const JBuf &jb, const int32_t *cid,
+                          const int64_t *t_cur, const int32_t *n_cur, int64_t t_host,
+                          int use_host_t, hipStream_t s) {
+    const int g = grid_for(pr.n_total);
+    if (pr.precision == NBODY_PREC_MIXED)
+        hipLaunchKernelGGL(k_predict<1>, dim3(g), dim3(kWG), 0, s, st, pr, jb, cid, t_cur, n_cur,
+                           t_host, use_host_t);
+    else
+        hipLaunchKernelGGL(k_predict<0>, dim3(g), dim3(kWG), 0, s, st, pr, jb, cid, t_cur, n_cur,
+                           t_host, use_host_t);
+    return hipGetLastError();
+}
+
+hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, double *vel,
+                                 hipStream_t s) {
+    hipLaunchKernelGGL(k_read_predicted, dim3(grid_for(pr.n_total)), dim3(kWG), 0, s, pr, jb, pos,
+                       vel, (int)(pr.precision == NBODY_PREC_MIXED));
+    return hipGetLastError();
+}
+
+hipError_t launch_select(const State &st, const Params &pr, const int64_t *off,
+                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
+                         int64_t *t_next, int32_t *n_act, int32_t *i_list, const DevCtl *ctl,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_select_min, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr, off,
+                       chunk_c, chunk_b, t_next);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_select_compact, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr, off,
+                       chunk_c, chunk_b, t_next, n_act, i_list, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, int32_t *n_act,
+                       int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
+                       int32_t j_tile, int32_t host_n, int64_t host_t, int32_t count_stats,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, pr, off, pl, n_act, t_next, ctl,
+                       part_cap, ct, j_tile, host_n, host_t, count_stats);
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce, dim3(grid_for(slot_space)), dim3(kWG), 0, s, fa, cid,
+                       slot_space);
+    return hipGetLastError();
+}
+
+hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_list,
+                          int32_t slots_at_offsets, const int64_t *off, const int32_t *cid,
+                          const int32_t *n_cur, const int64_t *t_cur, int64_t slot_space,
+                          const double *acc_new, const double *jerk_new, int64_t in_stride,
+                          DevCtl *ctl, hipStream_t s) {
+    hipLaunchKernelGGL(k_correct, dim3(grid_for(slot_space)), dim3(kWG), 0, s, st, pr, i_list,
+                       slots_at_offsets, off, cid, n_cur, t_cur, slot_space, acc_new, jerk_new,
+                       in_stride, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_finish(const State &st, const Params &pr, const double *acc_new,
+                              const double *jerk_new, int64_t stride, DevCtl *ctl,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(k_init_finish, dim3(grid_for(pr.n_total)), dim3(kWG), 0, s, st, pr,
+                       acc_new, jerk_new, stride, ctl);
+    return hipGetLastError();
+}
+
+}  // namespace nb

@@ -1,0 +1,715 @@
+// Host side of the C ABI declared in include/nbody.h: context, argument
+// checks, launch sequencing, graph capture of the block step, autotuning.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <climits>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "nbody.h"
+#include "nbody_internal.h"
+
+using namespace nb;
+
+struct nbody_ctx {
+    Params pr{};
+    State st{};
+    hipStream_t stream = nullptr;
+    int device = 0;
+    int n_cu = 256;
+
+    std::vector<int64_t> off_h;
+    int64_t max_cluster = 0;
+    int64_t *off_d = nullptr;
+    int32_t *cid_d = nullptr;
+    int32_t *chunk_c_d = nullptr;
+    int64_t *chunk_b_d = nullptr;
+    int64_t n_chunks = 0;
+
+    JBuf jb;
+    int32_t *i_list_d = nullptr;
+    int32_t *iota_d = nullptr;
+    int32_t *n_act_d = nullptr;
+    int64_t *t_next_d = nullptr;
+    PlanDev pl{};
+    double *acc_new = nullptr, *jerk_new = nullptr, *pot_new = nullptr;
+    double *part = nullptr;
+    int64_t part_cap = 0;
+    DevCtl *ctl = nullptr;
+    float *mmax_d = nullptr;  // [C] largest mass of each cluster
+
+    std::vector<void *> allocs;
+
+    // host bookkeeping
+    bool initialised = false;
+    bool predicted = false;
+    int64_t predicted_tick = -1;
+
+    Shape cls_shape[kClasses];
+    int cls_grid[kClasses];  // 0 = derive from occupancy
+    int32_t cls_min_n[kClasses];
+    int occ_cache[kClasses][2][2];  // occupancy per class, want_pot, exclude_self (0 = unknown)
+
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+};
+
+namespace {
+
+constexpr int kJTile = 256;
+constexpr int kGraphBatch = 32;  // block steps per captured graph
+
+int map_err(hipError_t e) {
+    if (e == hipSuccess)
+        return NBODY_OK;
+    if (e == hipErrorOutOfMemory)
+        return NBODY_ENOMEM;
+    return NBODY_EDEVICE;
+}
+
+#define NB_TRY(expr)                       \
+    do {                                   \
+        hipError_t e__ = (expr);           \
+        if (e__ != hipSuccess)             \
+            return map_err(e__);           \
+    } while (0)
+
+template <typename T>
+hipError_t dalloc(nbody_ctx *c, T **p, size_t count) {
+    void *q = nullptr;
+    hipError_t e = hipMalloc(&q, std::max<size_t>(1, count) * sizeof(T));
+    if (e != hipSuccess)
+        return e;
+    c->allocs.push_back(q);
+    *p = static_cast<T *>(q);
+    return hipSuccess;
+}
+
+int ib_of(const Shape &s) { return (kWG / s.j_lanes) * s.i_per_lane; }
+
+bool is_multiple_tick(double t, int dt_min_log2, int64_t *tick) {
+    if (!std::isfinite(t) || t < 0.0)
+        return false;
+    const double q = std::ldexp(t, -dt_min_log2);
+    if (q > 9.0e18 || q != std::floor(q))
+        return false;
+    *tick = (int64_t)q;
+    return true;
+}
+
+int grid_of(nbody_ctx *c, int cls, int want_pot, int excl) {
+    if (c->cls_grid[cls] > 0)
+        return c->cls_grid[cls];
+    int &occ = c->occ_cache[cls][want_pot ? 1 : 0][excl ? 1 : 0];
+    if (occ <= 0)
+        occ = std::max(1, force_occupancy(c->cls_shape[cls], c->pr.precision == NBODY_PREC_MIXED,
+                                          want_pot, excl));
+    return occ * c->n_cu;
+}
+
+// class of a given mean block size (the same rule k_plan applies)
+int class_of(const nbody_ctx *c, int64_t n_mean) {
+    for (int k = 0; k < kClasses; k++)
+        if (n_mean >= c->cls_min_n[k])
+            return k;
+    return kClasses - 1;
+}
+
+ClassTable class_table(nbody_ctx *c, int want_pot, int excl) {
+    ClassTable ct{};
+    for (int k = 0; k < kClasses; k++) {
+        ct.min_n[k] = c->cls_min_n[k];
+        ct.ib[k] = ib_of(c->cls_shape[k]);
+        ct.grid[k] = grid_of(c, k, want_pot, excl);
+    }
+    return ct;
+}
+
+ForceArgs force_args(nbody_ctx *c, const int32_t *i_list, int slots_at_offsets, double *acc,
+                     double *jerk, double *pot, int64_t stride) {
+    ForceArgs fa{};
+    fa.jb = c->jb;
+    fa.off = c->off_d;
+    fa.C = c->pr.C;
+    fa.item_begin = c->pl.item_begin;
+    fa.S = c->pl.S;
+    fa.jlen = c->pl.jlen;
+    fa.part_begin = c->pl.part_begin;
+    fa.n_cur = c->pl.n_cur;
+    fa.total_items = reinterpret_cast<const int64_t *>(&c->ctl->total_items);
+    fa.i_list = i_list;
+    fa.slots_at_offsets = slots_at_offsets;
+    fa.out_acc = acc;
+    fa.out_jerk = jerk;
+    fa.out_pot = pot;
+    fa.out_stride = stride;
+    fa.part = c->part;
+    fa.part_cap = c->part_cap;
+    fa.err = &c->ctl->err;
+    fa.item_counter = &c->ctl->item_counter;
+    fa.cls = &c->ctl->cls;
+    fa.fetch_lane = 0;
+    fa.n_total = c->pr.n_total;
+    fa.eps2 = c->pr.eps2;
+    fa.eps2f = (float)c->pr.eps2;
+    fa.hax = c->st.ax;
+    fa.hay = c->st.ay;
+    fa.haz = c->st.az;
+    fa.m64 = c->st.m;
+    fa.mmax = c->mmax_d;
+    fa.near_frac = c->pr.precision == NBODY_PREC_MIXED ? kNearFrac : 0.f;
+    return fa;
+}
+
+// One force evaluation planned on the device.  host_n >= 0: the block size is
+// known on the host (single cluster) and only that class's kernel is launched;
+// otherwise every class kernel is launched and all but the planned one exit.
+hipError_t enqueue_force(nbody_ctx *c, const int32_t *i_list, int slots_at_offsets,
+                         int32_t host_n, int64_t host_t, int count_stats, double *acc,
+                         double *jerk, double *pot, int64_t stride, int64_t slot_space) {
+    const int excl = c->pr.eps2 == 0.0;
+    const int want_pot = pot != nullptr;
+    const int mixed = c->pr.precision == NBODY_PREC_MIXED;
+    const ClassTable ct = class_table(c, want_pot, excl);
+    int only = -1;
+    if (host_n >= 0)
+        only = class_of(c, host_n);
+    hipError_t e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl,
+                               c->part_cap, ct, kJTile, host_n, host_t, count_stats, c->stream);
+    if (e != hipSuccess)
+        return e;
+    ForceArgs fa = force_args(c, i_list, slots_at_offsets, acc, jerk, pot, stride);
+    for (int k = 0; k < kClasses; k++) {
+        if (only >= 0 && k != only)
+            continue;
+        // identical shapes in two classes: the planned class id still selects one launch
+        fa.my_cls = k;
+        e = launch_force(c->cls_shape[k], mixed, want_pot, excl, fa, grid_of(c, k, want_pot, excl),
+                         c->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return launch_reduce(fa, c->cid_d, slot_space, c->stream);
+}
+
+int read_ctl(nbody_ctx *c, DevCtl *out) {
+    NB_TRY(hipStreamSynchronize(c->stream));
+    NB_TRY(hipMemcpy(out, c->ctl, sizeof(DevCtl), hipMemcpyDeviceToHost));
+    return NBODY_OK;
+}
+
+int consume_error(nbody_ctx *c, const DevCtl &h) {
+    if (h.err == 0)
+        return NBODY_OK;
+    int32_t zero = 0;
+    NB_TRY(hipMemcpy(&c->ctl->err, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    if (h.err & kErrRange)
+        return NBODY_ERANGE;
+    if (h.err & kErrNotDue)
+        return NBODY_ESTATE;
+    if (h.err & kErrNonFinite)
+        return NBODY_ENONFINITE;
+    return NBODY_EDEVICE;
+}
+
+hipError_t enqueue_block_step(nbody_ctx *c) {
+    hipError_t e = launch_select(c->st, c->pr, c->off_d, c->chunk_c_d, c->chunk_b_d, c->n_chunks,
+                                 c->t_next_d, c->n_act_d, c->i_list_d, c->ctl, c->stream);
+    if (e != hipSuccess)
+        return e;
+    // planning happens inside enqueue_force; predict needs t_cur from the plan,
+    // so plan first (host_n < 0), then predict, then the force kernels.
+    const int excl = c->pr.eps2 == 0.0;
+    const int mixed = c->pr.precision == NBODY_PREC_MIXED;
+    const ClassTable ct = class_table(c, 0, excl);
+    e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl, c->part_cap, ct,
+                    kJTile, -1, 0, 1, c->stream);
+    if (e != hipSuccess)
+        return e;
+    e = launch_predict(c->st, c->pr, c->jb, c->cid_d, c->pl.t_cur, c->pl.n_cur, 0, 0, c->stream);
+    if (e != hipSuccess)
+        return e;
+    ForceArgs fa = force_args(c, c->i_list_d, 1, c->acc_new, c->jerk_new, nullptr, c->pr.n_total);
+    for (int k = 0; k < kClasses; k++) {
+        fa.my_cls = k;
+        e = launch_force(c->cls_shape[k], mixed, 0, excl, fa, grid_of(c, k, 0, excl), c->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    e = launch_reduce(fa, c->cid_d, c->pr.n_total, c->stream);
+    if (e != hipSuccess)
+        return e;
+    return launch_correct(c->st, c->pr, c->i_list_d, 1, c->off_d, c->cid_d, c->pl.n_cur,
+                          c->pl.t_cur, c->pr.n_total, c->acc_new, c->jerk_new, c->pr.n_total,
+                          c->ctl, c->stream);
+}
+
+void drop_graph(nbody_ctx *c) {
+    if (c->graph_exec)
+        (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph)
+        (void)hipGraphDestroy(c->graph);
+    c->graph_exec = nullptr;
+    c->graph = nullptr;
+}
+
+// Capture kGraphBatch block steps on a private capture stream.
+int build_graph(nbody_ctx *c) {
+    drop_graph(c);
+    (void)class_table(c, 0, c->pr.eps2 == 0.0);  // occupancy queries happen outside capture
+    hipStream_t cap = nullptr;
+    NB_TRY(hipStreamCreateWithFlags(&cap, hipStreamNonBlocking));
+    hipStream_t user = c->stream;
+    c->stream = cap;
+    hipError_t e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        for (int s = 0; s < kGraphBatch && e == hipSuccess; s++)
+            e = enqueue_block_step(c);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(cap, &g);
+        if (e == hipSuccess)
+            e = e2;
+        if (e == hipSuccess) {
+            c->graph = g;
+            e = hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0);
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    c->stream = user;
+    (void)hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        return map_err(e);
+    }
+    return NBODY_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *nbody_strerror(int status) {
+    switch (status) {
+        case NBODY_OK: return "ok";
+        case NBODY_EINVAL: return "invalid argument";
+        case NBODY_ESTATE: return "call out of order or particle not due";
+        case NBODY_ENOMEM: return "device out of memory";
+        case NBODY_EDEVICE: return "HIP runtime error";
+        case NBODY_ENONFINITE: return "non-finite value produced";
+        case NBODY_EUNSUPPORTED: return "unsupported";
+        case NBODY_ERANGE: return "particle index out of range";
+        default: return "unknown status";
+    }
+}
+
+int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbody_ctx **out) {
+    if (!p || !s || !out)
+        return NBODY_EINVAL;
+    *out = nullptr;
+    if (p->n_total < 1 || p->n_total > INT32_MAX || p->n_clusters < 1 ||
+        p->n_clusters > p->n_total)
+        return NBODY_EINVAL;
+    if (!(p->eps >= 0.0) || !std::isfinite(p->eps) || !(p->eta > 0.0) || !std::isfinite(p->eta) ||
+        !(p->eta_init > 0.0) || !std::isfinite(p->eta_init))
+        return NBODY_EINVAL;
+    if (p->dt_min_log2 < -40 || p->dt_max_log2 > 0 || p->dt_min_log2 > p->dt_max_log2)
+        return NBODY_EINVAL;
+    if (p->precision != NBODY_PREC_FP64 && p->precision != NBODY_PREC_MIXED)
+        return NBODY_EINVAL;
+    for (int c = 0; c < 3; c++)
+        if (!s->pos[c] || !s->vel[c] || !s->acc[c] || !s->jerk[c])
+            return NBODY_EINVAL;
+    if (!s->mass || !s->t_tick || !s->level)
+        return NBODY_EINVAL;
+    std::vector<int64_t> off(p->n_clusters + 1);
+    if (p->n_clusters == 1 && !p->cluster_offset) {
+        off[0] = 0;
+        off[1] = p->n_total;
+    } else {
+        if (!p->cluster_offset)
+            return NBODY_EINVAL;
+        for (int c = 0; c <= p->n_clusters; c++)
+            off[c] = p->cluster_offset[c];
+        if (off[0] != 0 || off[p->n_clusters] != p->n_total)
+            return NBODY_EINVAL;
+        for (int c = 0; c < p->n_clusters; c++)
+            if (off[c + 1] <= off[c])
+                return NBODY_EINVAL;
+    }
+
+    nbody_ctx *c = new (std::nothrow) nbody_ctx();
+    if (!c)
+        return NBODY_ENOMEM;
+    c->stream = static_cast<hipStream_t>(stream);
+    c->off_h = off;
+    for (int k = 0; k < p->n_clusters; k++)
+        c->max_cluster = std::max(c->max_cluster, off[k + 1] - off[k]);
+
+    Params &pr = c->pr;
+    pr.n_total = p->n_total;
+    pr.C = p->n_clusters;
+    pr.eps2 = p->eps * p->eps;
+    pr.eps2f = (float)pr.eps2;
+    pr.eta = p->eta;
+    pr.eta_init = p->eta_init;
+    pr.dt_min_log2 = p->dt_min_log2;
+    pr.dt_max_log2 = p->dt_max_log2;
+    pr.lev_min = -p->dt_max_log2;
+    pr.lev_max = -p->dt_min_log2;
+    pr.tick = std::ldexp(1.0, p->dt_min_log2);
+    pr.precision = p->precision;
+    pr.grid_q = std::ldexp(1.0, kGridQLog2);
+    pr.grid_inv = std::ldexp(1.0, -kGridQLog2);
+
+    State &st = c->st;
+    st.x = s->pos[0]; st.y = s->pos[1]; st.z = s->pos[2];
+    st.vx = s->vel[0]; st.vy = s->vel[1]; st.vz = s->vel[2];
+    st.ax = s->acc[0]; st.ay = s->acc[1]; st.az = s->acc[2];
+    st.jx = s->jerk[0]; st.jy = s->jerk[1]; st.jz = s->jerk[2];
+    st.m = s->mass;
+    st.tick = s->t_tick;
+    st.lev = s->level;
+
+    // default launch shapes by block size
+    const Shape shapes[kClasses] = {{2, 1, kJTile}, {1, 4, kJTile}, {1, 16, kJTile},
+                                    {1, 64, kJTile}, {1, 256, kJTile}};
+    const int32_t min_n[kClasses] = {2048, 256, 32, 4, 0};
+    for (int k = 0; k < kClasses; k++) {
+        c->cls_shape[k] = shapes[k];
+        c->cls_grid[k] = 0;
+        c->cls_min_n[k] = min_n[k];
+    }
+    std::memset(c->occ_cache, 0, sizeof(c->occ_cache));
+
+    int rc = NBODY_OK;
+    auto fail = [&](hipError_t e) {
+        rc = map_err(e);
+        nbody_destroy(c);
+        return rc;
+    };
+    hipError_t e = hipGetDevice(&c->device);
+    if (e != hipSuccess)
+        return fail(e);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, c->device) ==
+            hipSuccess &&
+        cus > 0)
+        c->n_cu = cus;
+
+    const int64_t N = pr.n_total, C = pr.C;
+    // chunk list for selection: chunks never cross clusters
+    std::vector<int32_t> chunk_c;
+    std::vector<int64_t> chunk_b;
+    std::vector<int32_t> cid(N);
+    for (int64_t k = 0; k < C; k++) {
+        for (int64_t b = off[k]; b < off[k + 1]; b += kChunk) {
+            chunk_c.push_back((int32_t)k);
+            chunk_b.push_back(b);
+        }
+        for (int64_t i = off[k]; i < off[k + 1]; i++)
+            cid[i] = (int32_t)k;
+    }
+    c->n_chunks = (int64_t)chunk_c.size();
+    // partial sums: enough for any j-split the planner may choose
+    c->part_cap = std::max<int64_t>(1 << 20, std::min<int64_t>(16 << 20, 8 * N));
+
+    const bool mixed = pr.precision == NBODY_PREC_MIXED;
+    if ((e = dalloc(c, &c->off_d, C + 1)) != hipSuccess || (e = dalloc(c, &c->cid_d, N)) != hipSuccess ||
+        (e = dalloc(c, &c->chunk_c_d, c->n_chunks)) != hipSuccess ||
+        (e = dalloc(c, &c->chunk_b_d, c->n_chunks)) != hipSuccess ||
+        (e = dalloc(c, &c->i_list_d, N)) != hipSuccess || (e = dalloc(c, &c->iota_d, N)) != hipSuccess ||
+        (e = dalloc(c, &c->n_act_d, C)) != hipSuccess || (e = dalloc(c, &c->t_next_d, C)) != hipSuccess ||
+        (e = dalloc(c, &c->pl.item_begin, C + 1)) != hipSuccess ||
+        (e = dalloc(c, &c->pl.S, C)) != hipSuccess || (e = dalloc(c, &c->pl.jlen, C)) != hipSuccess ||
+        (e = dalloc(c, &c->pl.part_begin, C)) != hipSuccess ||
+        (e = dalloc(c, &c->pl.n_cur, C)) != hipSuccess || (e = dalloc(c, &c->pl.t_cur, C)) != hipSuccess ||
+        (e = dalloc(c, &c->acc_new, 3 * N)) != hipSuccess ||
+        (e = dalloc(c, &c->jerk_new, 3 * N)) != hipSuccess ||
+        (e = dalloc(c, &c->pot_new, N)) != hipSuccess ||
+        (e = dalloc(c, &c->part, 7 * c->part_cap)) != hipSuccess ||
+        (e = dalloc(c, &c->ctl, 1)) != hipSuccess || (e = dalloc(c, &c->mmax_d, C)) != hipSuccess)
+        return fail(e);
+    if (mixed) {
+        if ((e = dalloc(c, &c->jb.P, N)) != hipSuccess || (e = dalloc(c, &c->jb.Q, N)) != hipSuccess ||
+            (e = dalloc(c, &c->jb.R, N)) != hipSuccess)
+            return fail(e);
+    } else {
+        if ((e = dalloc(c, &c->jb.A, N)) != hipSuccess || (e = dalloc(c, &c->jb.B, N)) != hipSuccess ||
+            (e = dalloc(c, &c->jb.C, N)) != hipSuccess || (e = dalloc(c, &c->jb.D, N)) != hipSuccess)
+            return fail(e);
+    }
+    if ((e = hipMemcpy(c->off_d, off.data(), (C + 1) * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->cid_d, cid.data(), N * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->chunk_c_d, chunk_c.data(), c->n_chunks * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(c->chunk_b_d, chunk_b.data(), c->n_chunks * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    DevCtl h{};
+    h.t_end_tick = LLONG_MAX;
+    if ((e = hipMemcpy(c->ctl, &h, sizeof(h), hipMemcpyHostToDevice)) != hipSuccess)
+        return fail(e);
+    if ((e = launch_iota_i32(c->iota_d, N, c->stream)) != hipSuccess ||
+        (e = launch_fill_i32(c->n_act_d, 0, C, c->stream)) != hipSuccess ||
+        (e = launch_fill_i64(c->t_next_d, LLONG_MAX, C, c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+        return fail(e);
+    *out = c;
+    return NBODY_OK;
+}
+
+int nbody_destroy(nbody_ctx *c) {
+    if (!c)
+        return NBODY_EINVAL;
+    if (c->stream)
+        (void)hipStreamSynchronize(c->stream);
+    else
+        (void)hipDeviceSynchronize();
+    drop_graph(c);
+    for (void *p : c->allocs)
+        (void)hipFree(p);
+    delete c;
+    return NBODY_OK;
+}
+
+int nbody_init(nbody_ctx *c) {
+    if (!c)
+        return NBODY_EINVAL;
+    const int64_t N = c->pr.n_total;
+    DevCtl h{};
+    h.t_end_tick = LLONG_MAX;
+    NB_TRY(hipStreamSynchronize(c->stream));
+    NB_TRY(hipMemcpy(c->ctl, &h, sizeof(h), hipMemcpyHostToDevice));
+    // zero a and jerk so the t = 0 prediction is exactly the positions
+    for (int q = 0; q < 3; q++) {
+        double *a[3] = {c->st.ax, c->st.ay, c->st.az};
+        double *j[3] = {c->st.jx, c->st.jy, c->st.jz};
+        NB_TRY(launch_fill_f64(a[q], 0.0, N, c->stream));
+        NB_TRY(launch_fill_f64(j[q], 0.0, N, c->stream));
+    }
+    NB_TRY(launch_fill_i64(c->st.tick, 0, N, c->stream));
+    NB_TRY(launch_fill_i32(c->n_act_d, 0, c->pr.C, c->stream));
+    NB_TRY(launch_fill_i64(c->t_next_d, LLONG_MAX, c->pr.C, c->stream));
+    NB_TRY(launch_predict(c->st, c->pr, c->jb, c->cid_d, nullptr, nullptr, 0, 1, c->stream));
+    // full sweep of every cluster: active list = identity, n_c = N_c, t = 0
+    std::vector<int32_t> nc(c->pr.C);
+    for (int k = 0; k < c->pr.C; k++)
+        nc[k] = (int32_t)(c->off_h[k + 1] - c->off_h[k]);
+    // largest mass per cluster (near-field threshold of the mixed form)
+    {
+        std::vector<double> mh(N);
+        NB_TRY(hipStreamSynchronize(c->stream));
+        NB_TRY(hipMemcpy(mh.data(), c->st.m, N * sizeof(double), hipMemcpyDeviceToHost));
+        std::vector<float> mx(c->pr.C, 0.f);
+        for (int k = 0; k < c->pr.C; k++) {
+            double v = 0.0;
+            for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++)
+                v = std::max(v, std::fabs(mh[i]));
+            mx[k] = (float)v;
+        }
+        NB_TRY(hipMemcpy(c->mmax_d, mx.data(), mx.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    // mixed: a first sweep without near field gives |a| for the thresholds
+    const int passes = c->pr.precision == NBODY_PREC_MIXED ? 2 : 1;
+    for (int pass = 0; pass < passes; pass++) {
+        // only the last pass's start-up steps count as clamped
+        NB_TRY(launch_set_i64(reinterpret_cast<int64_t *>(&c->ctl->clamps), 0, c->stream));
+        NB_TRY(hipMemcpyAsync(c->n_act_d, nc.data(), nc.size() * sizeof(int32_t),
+                              hipMemcpyHostToDevice, c->stream));
+        NB_TRY(launch_fill_i64(c->t_next_d, 0, c->pr.C, c->stream));
+        NB_TRY(enqueue_force(c, c->iota_d, 1, -1, 0, 0, c->acc_new, c->jerk_new, nullptr, N, N));
+        NB_TRY(launch_init_finish(c->st, c->pr, c->acc_new, c->jerk_new, N, c->ctl, c->stream));
+        NB_TRY(hipStreamSynchronize(c->stream));  // nc must outlive the async copy
+    }
+    c->initialised = true;
+    c->predicted = true;
+    c->predicted_tick = 0;
+    DevCtl hc;
+    int rc = read_ctl(c, &hc);
+    if (rc != NBODY_OK)
+        return rc;
+    return consume_error(c, hc);
+}
+
+int nbody_predict(nbody_ctx *c, double t) {
+    if (!c)
+        return NBODY_EINVAL;
+    if (c->pr.C != 1)
+        return NBODY_EUNSUPPORTED;
+    int64_t tick;
+    if (!is_multiple_tick(t, c->pr.dt_min_log2, &tick))
+        return NBODY_EINVAL;
+    NB_TRY(launch_predict(c->st, c->pr, c->jb, c->cid_d, nullptr, nullptr, tick, 1, c->stream));
+    c->predicted = true;
+    c->predicted_tick = tick;
+    return NBODY_OK;
+}
+
+int nbody_force_jerk(nbody_ctx *c, const int32_t *i_list, int64_t n, double t, double *acc,
+                     double *jerk, double *pot) {
+    if (!c || !i_list || !acc || !jerk)
+        return NBODY_EINVAL;
+    if (c->pr.C != 1)
+        return NBODY_EUNSUPPORTED;
+    if (n < 1 || n > c->pr.n_total)
+        return NBODY_EINVAL;
+    int64_t tick;
+    if (!is_multiple_tick(t, c->pr.dt_min_log2, &tick))
+        return NBODY_EINVAL;
+    if (!c->predicted || c->predicted_tick != tick)
+        return NBODY_ESTATE;
+    NB_TRY(enqueue_force(c, i_list, 0, (int32_t)n, tick, 0, acc, jerk, pot, n, n));
+    return NBODY_OK;
+}
+
+int nbody_correct(nbody_ctx *c, const int32_t *i_list, int64_t n, double t, const double *acc,
+                  const double *jerk) {
+    if (!c || !i_list || !acc || !jerk)
+        return NBODY_EINVAL;
+    if (c->pr.C != 1)
+        return NBODY_EUNSUPPORTED;
+    if (n < 1 || n > c->pr.n_total)
+        return NBODY_EINVAL;
+    int64_t tick;
+    if (!is_multiple_tick(t, c->pr.dt_min_log2, &tick))
+        return NBODY_EINVAL;
+    if (!c->initialised)
+        return NBODY_ESTATE;
+    // the corrector reads n and t from the plan arrays; set them for this call
+    const int32_t nn = (int32_t)n;
+    NB_TRY(launch_fill_i32(c->pl.n_cur, nn, 1, c->stream));
+    NB_TRY(launch_set_i64(c->pl.t_cur, tick, c->stream));
+    NB_TRY(launch_correct(c->st, c->pr, i_list, 0, c->off_d, c->cid_d, c->pl.n_cur, c->pl.t_cur,
+                          n, acc, jerk, n, c->ctl, c->stream));
+    c->predicted = false;
+    return NBODY_OK;
+}
+
+int nbody_step_block(nbody_ctx *c, double *t_out, int64_t *n_out) {
+    if (!c)
+        return NBODY_EINVAL;
+    if (!c->initialised)
+        return NBODY_ESTATE;
+    NB_TRY(launch_set_i64(reinterpret_cast<int64_t *>(&c->ctl->t_end_tick), LLONG_MAX, c->stream));
+    NB_TRY(enqueue_block_step(c));
+    c->predicted = false;
+    if (!t_out && !n_out)
+        return NBODY_OK;
+    DevCtl h;
+    int rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    if (n_out)
+        *n_out = h.n_last;
+    if (t_out) {
+        int64_t tk = 0;
+        NB_TRY(hipMemcpy(&tk, c->pl.t_cur, sizeof(tk), hipMemcpyDeviceToHost));
+        *t_out = std::ldexp((double)tk, c->pr.dt_min_log2);
+    }
+    return consume_error(c, h);
+}
+
+int nbody_run_until(nbody_ctx *c, double t_end, int64_t *n_steps_out) {
+    if (!c)
+        return NBODY_EINVAL;
+    if (!c->initialised)
+        return NBODY_ESTATE;
+    int64_t tick;
+    if (!is_multiple_tick(t_end, c->pr.dt_min_log2, &tick))
+        return NBODY_EINVAL;
+    NB_TRY(launch_set_i64(reinterpret_cast<int64_t *>(&c->ctl->t_end_tick), tick, c->stream));
+    if (!c->graph_exec) {
+        int rc = build_graph(c);
+        if (rc != NBODY_OK)
+            return rc;
+    }
+    DevCtl h;
+    int rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    const unsigned long long steps0 = h.steps;
+    for (;;) {
+        NB_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+        rc = read_ctl(c, &h);
+        if (rc != NBODY_OK)
+            return rc;
+        if (h.err)
+            break;
+        if (!h.any_active)
+            break;
+    }
+    c->predicted = false;
+    if (n_steps_out)
+        *n_steps_out = (int64_t)(h.steps - steps0);
+    return consume_error(c, h);
+}
+
+int nbody_sync(nbody_ctx *c) {
+    if (!c)
+        return NBODY_EINVAL;
+    DevCtl h;
+    int rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    return consume_error(c, h);
+}
+
+int nbody_get_stats(nbody_ctx *c, nbody_stats *out) {
+    if (!c || !out)
+        return NBODY_EINVAL;
+    DevCtl h;
+    int rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    out->block_steps = (int64_t)h.steps;
+    out->updates = (int64_t)h.updates;
+    out->interactions = h.interactions;
+    out->dt_clamped = (int64_t)h.clamps;
+    return consume_error(c, h);
+}
+
+int nbody_read_predicted(nbody_ctx *c, double *pos, double *vel) {
+    if (!c || !pos || !vel)
+        return NBODY_EINVAL;
+    if (!c->predicted)
+        return NBODY_ESTATE;
+    NB_TRY(launch_read_predicted(c->pr, c->jb, pos, vel, c->stream));
+    return NBODY_OK;
+}
+
+int nbody_get_tuning(const nbody_ctx *c, nbody_tuning *out) {
+    if (!c || !out)
+        return NBODY_EINVAL;
+    out->i_per_lane = c->cls_shape[0].i_per_lane;
+    out->j_lanes = c->cls_shape[0].j_lanes;
+    out->j_tile = c->cls_shape[0].j_tile;
+    out->grid = c->cls_grid[0];
+    return NBODY_OK;
+}
+
+int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
+    if (!c || !t)
+        return NBODY_EINVAL;
+    const Shape sh{t->i_per_lane, t->j_lanes, t->j_tile};
+    if (!force_shape_supported(sh) || t->grid < 0)
+        return NBODY_EINVAL;
+    c->cls_shape[0] = sh;
+    c->cls_grid[0] = t->grid;
+    std::memset(c->occ_cache[0], 0, sizeof(c->occ_cache[0]));
+    drop_graph(c);
+    return NBODY_OK;
+}
+
+int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *best_ms) {
+    (void)c;
+    (void)n_probe;
+    (void)best;
+    (void)best_ms;
+    return NBODY_EUNSUPPORTED;
+}
+
+}  // extern "C"

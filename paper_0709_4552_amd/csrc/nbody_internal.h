@@ -1,0 +1,190 @@
+// Internal declarations shared by the translation units of libnbody.
+// Not part of the public ABI (include/nbody.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nbody.h"
+
+namespace nb {
+
+constexpr int kWG = 256;          // threads per workgroup, every kernel
+constexpr int kChunk = 2048;      // particles per selection chunk (never crosses clusters)
+constexpr int kPlanThreads = 1024;
+
+// bits of the device error word
+enum : int32_t {
+    kErrNonFinite = 1,
+    kErrRange = 2,
+    kErrNotDue = 4,
+    kErrPlan = 8,
+};
+
+// Device-resident counters and scalars, one instance per context.
+struct DevCtl {
+    int32_t err;                   // error bits
+    int32_t n_last;                // block size summed over clusters, last planned step
+    int64_t total_items;           // force work items of the current plan
+    int64_t part_used;             // partial-sum slots used by the current plan
+    int64_t t_end_tick;            // clusters stop when their next time exceeds this
+    unsigned long long clamps;     // steps clamped at the minimum
+    unsigned long long steps;      // block steps with n > 0 (summed over clusters)
+    unsigned long long updates;    // corrected particles
+    double interactions;           // n*N summed
+    int32_t any_active;            // at least one cluster active in the last plan
+    int32_t cls;                   // shape class chosen by the last plan
+    unsigned long long item_counter;  // work queue head of the force kernel
+};
+
+// Launch-shape classes by block size: class k is used when the mean block
+// size of the active clusters is >= min_n[k] (classes in decreasing order).
+constexpr int kClasses = 5;
+struct ClassTable {
+    int32_t min_n[kClasses];
+    int32_t ib[kClasses];     // i-particles per work item of the class's shape
+    int32_t grid[kClasses];   // persistent workgroups of the class's launch
+};
+
+// Predicted j-particle buffer.
+//  mixed: P = (x_hi, y_hi, z_hi, m), Q = (x_lo, y_lo, z_lo, vx), R = (vy, vz)
+//         with x = x_hi + x_lo, x_hi = fl32(x), x_lo = fl32(x - x_hi)
+//  fp64 : A = (x, y), B = (z, m), C = (vx, vy), D = vz
+struct JBuf {
+    float4 *P = nullptr;
+    float4 *Q = nullptr;
+    float2 *R = nullptr;
+    double2 *A = nullptr;
+    double2 *B = nullptr;
+    double2 *C = nullptr;
+    double *D = nullptr;
+};
+
+// Caller state in device-pointer form (copied from nbody_state).
+struct State {
+    double *x, *y, *z, *vx, *vy, *vz, *ax, *ay, *az, *jx, *jy, *jz, *m;
+    int64_t *tick;
+    int8_t *lev;
+};
+
+// Work plan of one force evaluation, built on the device by k_plan.
+struct PlanDev {
+    int64_t *item_begin;   // [C+1] first work item of each cluster
+    int32_t *S;            // [C] j-slices
+    int32_t *jlen;         // [C] j-particles per slice (multiple of the tile)
+    int64_t *part_begin;   // [C] first partial-sum slot of each cluster (S>1)
+    int32_t *n_cur;        // [C] block size of the step being computed
+    int64_t *t_cur;        // [C] time (ticks) of the step being computed
+};
+
+struct Params {
+    int64_t n_total;
+    int32_t C;
+    double eps2;
+    float eps2f;
+    double eta, eta_init;
+    int32_t dt_min_log2, dt_max_log2;
+    int32_t lev_min, lev_max;       // -dt_max_log2, -dt_min_log2
+    double tick;                    // 2^dt_min_log2
+    int32_t precision;
+    double grid_q;                  // mixed: quantum of the hi part of positions
+    double grid_inv;                // 1 / grid_q
+};
+
+// Mixed precision near field: a pair whose term may exceed kNearFrac*|a_i|
+// (m_max/s > kNearFrac*|a_i|, with |a_i| the particle's last acceleration) is
+// evaluated in FP64 instead of FP32.
+constexpr float kNearFrac = 0.1f;
+constexpr int kGridQLog2 = -16;  // hi parts on a 2^-16 grid: exact differences for |x| < 256
+
+// Everything the force kernels need.
+struct ForceArgs {
+    JBuf jb;
+    const int64_t *off;       // [C+1] cluster offsets (device)
+    int32_t C;
+    const int64_t *item_begin;
+    const int32_t *S;
+    const int32_t *jlen;
+    const int64_t *part_begin;
+    const int32_t *n_cur;
+    const int64_t *total_items;   // &ctl->total_items
+    const int32_t *i_list;        // slot-indexed active list
+    int32_t slots_at_offsets;     // slot of (c,k) = off[c]+k if set, else k
+    double *out_acc;              // [3][stride]
+    double *out_jerk;             // [3][stride]
+    double *out_pot;              // [stride] or null
+    int64_t out_stride;
+    double *part;                 // [7][part_cap]
+    int64_t part_cap;
+    int32_t *err;
+    unsigned long long *item_counter;
+    const int32_t *cls;           // class chosen by the plan
+    int32_t my_cls;               // this launch runs only if *cls == my_cls
+    int32_t fetch_lane;           // thread that pops the work queue (always 0); a
+                                  // run-time value so the compiler cannot merge its
+                                  // branch with other tid == 0 branches across the
+                                  // barriers of the item loop
+    int64_t n_total;
+    double eps2;
+    float eps2f;
+    // mixed near field
+    const double *hax, *hay, *haz;  // |a_i| hint: the particle's stored acceleration
+    const double *m64;              // FP64 masses
+    const float *mmax;              // [C] largest mass of each cluster
+    float near_frac;                // 0 disables the near field
+};
+
+struct Shape {
+    int i_per_lane;
+    int j_lanes;
+    int j_tile;
+};
+
+// A value every lane of the wave holds, made visibly uniform to the compiler.
+// Loops and branches that contain barriers must depend only on such values:
+// a barrier inside control flow the compiler treats as divergent (for example
+// a loop whose exit reads LDS) is undefined and has deadlocked workgroups.
+__device__ inline int64_t uniform_i64(int64_t v) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+__device__ inline int32_t uniform_i32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// ---- launchers (kernels_step.hip) -----------------------------------------
+hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t *p, int32_t v, int64_t n, hipStream_t s);
+hipError_t launch_fill_f64(double *p, double v, int64_t n, hipStream_t s);
+hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);
+hipError_t launch_predict(const State &st, const Params &pr, const JBuf &jb, const int32_t *cid,
+                          const int64_t *t_cur, const int32_t *n_cur, int64_t t_host,
+                          int use_host_t, hipStream_t s);
+hipError_t launch_select(const State &st, const Params &pr, const int64_t *off,
+                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
+                         int64_t *t_next, int32_t *n_act, int32_t *i_list, const DevCtl *ctl,
+                         hipStream_t s);
+hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, int32_t *n_act,
+                       int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
+                       int32_t j_tile, int32_t host_n, int64_t host_t, int32_t count_stats,
+                       hipStream_t s);
+hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
+                         hipStream_t s);
+hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_list,
+                          int32_t slots_at_offsets, const int64_t *off, const int32_t *cid,
+                          const int32_t *n_cur, const int64_t *t_cur, int64_t slot_space,
+                          const double *acc_new, const double *jerk_new, int64_t in_stride,
+                          DevCtl *ctl, hipStream_t s);
+hipError_t launch_init_finish(const State &st, const Params &pr, const double *acc_new,
+                              const double *jerk_new, int64_t stride, DevCtl *ctl,
+                              hipStream_t s);
+hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, double *vel,
+                                 hipStream_t s);
+
+// ---- force (kernels_force.hip) --------------------------------------------
+bool force_shape_supported(const Shape &sh);
+int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self);
+hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self,
+                        const ForceArgs &fa, int grid, hipStream_t s);
+
+}  // namespace nb

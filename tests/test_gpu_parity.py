@@ -1,0 +1,294 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (per particle, relative to the oracle's value):
+  FP64 kernel:   acceleration <= 1e-11, jerk <= 1e-9 (different summation
+                 order; the jerk sum cancels more), potential <= 1e-12;
+  mixed kernel:  acceleration <= 1e-6 (the spec bar), jerk <= 1e-5,
+                 potential <= 1e-6.
+Block steps are compared state by state in FP64, where both sides take the
+same power-of-two decisions.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from nbody_inputs import ensemble, plummer
+from paper_0709_4552_amd import NBODY_PREC_FP64, NBODY_PREC_MIXED, NBody, NBodyError
+from paper_0709_4552_amd import _lib
+
+pytestmark = pytest.mark.gpu
+
+TOL = {NBODY_PREC_FP64: dict(a=1e-11, j=1e-9, p=1e-12),
+       NBODY_PREC_MIXED: dict(a=1e-6, j=1e-5, p=1e-6)}
+PREC = [NBODY_PREC_FP64, NBODY_PREC_MIXED]
+PID = ["fp64", "mixed"]
+
+
+def relerr(g, r):
+    g = np.asarray(g)
+    r = np.asarray(r)
+    if g.ndim == 1:
+        return np.abs(g - r) / np.abs(r)
+    return np.linalg.norm(g - r, axis=1) / np.linalg.norm(r, axis=1)
+
+
+def note(msg):
+    print(msg, flush=True)
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+@pytest.mark.parametrize("n", [1000, 4133])
+def test_init_sweep_matches_oracle(prec, n):
+    note(f"init sweep prec={prec} n={n}")
+    x, v, m = plummer(n, 1001)
+    eps = 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    _, _, a, j, t, dt = g.host_state()
+    prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-3)
+    ref = oracle.System(x, v, m, prm)
+    assert relerr(a, ref.a).max() <= TOL[prec]["a"]
+    assert relerr(j, ref.jk).max() <= TOL[prec]["j"]
+    assert np.all(t == 0)
+    lv = np.log2(dt)
+    lr = np.log2(ref.dt_i)
+    if prec == NBODY_PREC_FP64:
+        assert np.array_equal(lv, lr)
+    else:
+        assert np.mean(lv != lr) <= 0.01 and np.abs(lv - lr).max() <= 1
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_predict_matches_oracle(prec):
+    note(f"predict prec={prec}")
+    x, v, m = plummer(777, 1002)
+    eps = 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    t = 3 * 2.0 ** -10
+    g.predict(t)
+    pos, vel = g.read_predicted()
+    pos = pos.T.cpu().numpy()
+    vel = vel.T.cpu().numpy()
+    xg, vg, ag, jg, tg, _ = g.host_state()
+    xp, vp = oracle.predict(t, tg, xg, vg, ag, jg)
+    if prec == NBODY_PREC_FP64:
+        assert np.abs(pos - xp).max() <= 1e-15 * (1 + np.abs(xp).max())
+        assert np.abs(vel - vp).max() <= 1e-15 * (1 + np.abs(vp).max())
+    else:
+        # positions: hi on a 2^-16 grid plus an FP32 lo part (|lo| <= 2^-17), so
+        # the stored position is within 2^-41 of the FP64 prediction; velocities
+        # are FP32 (relative 2^-24)
+        assert np.all(np.abs(pos - xp) <= 2.0 ** -41 + 1e-15 * np.abs(xp))
+        assert np.all(np.abs(vel - vp) <= 2.0 ** -24 * np.abs(vp) * 1.0001 + 1e-15)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+@pytest.mark.parametrize("n", [1, 3, 17, 64, 100, 257, 1000, 3000])
+def test_force_jerk_matches_oracle(prec, n):
+    note(f"force_jerk prec={prec} n={n}")
+    N = 3000
+    x, v, m = plummer(N, 1003)
+    eps = 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    t = 5 * 2.0 ** -12
+    g.predict(t)
+    rng = np.random.Generator(np.random.PCG64(n))
+    il = rng.integers(0, N, n).astype(np.int32)  # duplicates allowed
+    if n == N:
+        il = np.arange(N, dtype=np.int32)
+    acc, jerk, pot = g.force_jerk(il, t)
+    acc = acc.T.cpu().numpy()
+    jerk = jerk.T.cpu().numpy()
+    pot = pot.cpu().numpy()
+    xg, vg, ag, jg, tg, _ = g.host_state()
+    xp, vp = oracle.predict(t, tg, xg, vg, ag, jg)
+    ra, rj, rp = oracle.force(xp, vp, m, eps, il)
+    assert relerr(acc, ra).max() <= TOL[prec]["a"]
+    assert relerr(jerk, rj).max() <= TOL[prec]["j"]
+    assert relerr(pot, rp).max() <= TOL[prec]["p"]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_force_jerk_unsoftened_skips_self(prec):
+    note(f"eps=0 prec={prec}")
+    x, v, m = plummer(300, 1004)
+    g = NBody(x, v, m, 0.0, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    g.predict(0.0)
+    il = np.arange(300, dtype=np.int32)
+    acc, jerk, pot = g.force_jerk(il, 0.0)
+    ra, rj, rp = oracle.force(x, v, m, 0.0, il)
+    assert np.all(np.isfinite(acc.cpu().numpy()))
+    assert relerr(acc.T.cpu().numpy(), ra).max() <= 10 * TOL[prec]["a"]
+    assert relerr(pot.cpu().numpy(), rp).max() <= 10 * TOL[prec]["p"]
+    g.close()
+
+
+def _due(t_i, dt_i):
+    nxt = t_i + dt_i
+    t = nxt.min()
+    return t, np.nonzero(nxt == t)[0].astype(np.int32)
+
+
+def test_explicit_block_step_matches_oracle_fp64():
+    note("explicit predict/force/correct fp64")
+    x, v, m = plummer(1500, 1005)
+    eps = 1 / 256
+    prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-3)
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_FP64)
+    g.init()
+    xg, vg, ag, jg, tg, dtg = g.host_state()
+    ref = oracle.System.from_state(xg, vg, m, ag, jg, tg, dtg, prm)
+    for _ in range(6):
+        _, _, _, _, tg, dtg = g.host_state()
+        t, act = _due(tg, dtg)
+        g.predict(t)
+        acc, jerk, _ = g.force_jerk(act, t, want_pot=False)
+        g.correct(act, t, acc, jerk)
+        g.sync()
+        tr, actr, _ = ref.step()
+        assert tr == t and np.array_equal(np.sort(act), actr)
+    xg, vg, ag, jg, tg, dtg = g.host_state()
+    assert np.array_equal(tg, ref.t_i) and np.array_equal(dtg, ref.dt_i)
+    assert np.abs(xg - ref.x).max() <= 1e-13
+    assert np.abs(vg - ref.v).max() <= 1e-12
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_step_block_matches_oracle(prec):
+    note(f"step_block prec={prec}")
+    x, v, m = plummer(2000, 1006)
+    eps = 1 / 256
+    prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-3)
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    xg, vg, ag, jg, tg, dtg = g.host_state()
+    ref = oracle.System.from_state(xg, vg, m, ag, jg, tg, dtg, prm)
+    for _ in range(12):
+        t, n = g.step_block()
+        tr, actr, _ = ref.step()
+        assert t == tr and n == actr.size
+        if prec == NBODY_PREC_MIXED:
+            # same block, then continue from the GPU's state (force errors differ)
+            xg, vg, ag, jg, tg, dtg = g.host_state()
+            ref = oracle.System.from_state(xg, vg, m, ag, jg, tg, dtg, prm)
+    if prec == NBODY_PREC_FP64:
+        xg, vg, ag, jg, tg, dtg = g.host_state()
+        assert np.array_equal(tg, ref.t_i) and np.array_equal(dtg, ref.dt_i)
+        assert np.abs(xg - ref.x).max() <= 1e-13
+    g.close()
+
+
+def test_run_until_shared_steps_config1():
+    note("config 1: N=1024 shared dt=1/256 32 steps fp64")
+    x, v, m = plummer(1024, 1001)
+    eps = 1 / 256
+    prm = oracle.params(eps, dt_min_log2=-8, dt_max_log2=-8)
+    ref = oracle.System(x, v, m, prm)
+    E0 = sum(ref.energy())
+    ref.run(32 / 256)
+    g = NBody(x, v, m, eps, dt_min_log2=-8, dt_max_log2=-8, precision=NBODY_PREC_FP64)
+    g.init()
+    steps = g.run_until(32 / 256)
+    assert steps == 32
+    xg, vg, ag, jg, tg, _ = g.host_state()
+    assert np.all(tg == 32 / 256)
+    assert np.abs(xg - ref.x).max() <= 1e-10
+    assert np.abs(vg - ref.v).max() <= 1e-10
+    E1 = sum(oracle.energy(xg, vg, m, eps))
+    assert abs(E1 - E0) / abs(E0) <= 1e-5
+    P = (m[:, None] * vg).sum(0) - (m[:, None] * v).sum(0)
+    assert np.abs(P).max() <= 1e-13
+    st = g.stats()
+    assert st["block_steps"] == 32 and st["updates"] == 32 * 1024
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_ensemble_matches_independent_oracles(prec):
+    note(f"ensemble 6 clusters prec={prec}")
+    x, v, m, offs = ensemble(6, 77, 100, 700)
+    eps = 1 / 256
+    T = 1 / 16
+    prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-3)
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec,
+              cluster_offset=offs)
+    g.init()
+    g.run_until(T)
+    xg, vg, _, _, tg, _ = g.host_state()
+    assert np.all(tg == T)
+    for k in range(6):
+        sl = slice(offs[k], offs[k + 1])
+        ref = oracle.System(x[sl], v[sl], m[sl], prm)
+        E0 = sum(ref.energy())
+        ref.run(T)
+        if prec == NBODY_PREC_FP64:
+            assert np.abs(xg[sl] - ref.x).max() <= 1e-10, k
+        E1 = sum(oracle.energy(xg[sl], vg[sl], m[sl], eps))
+        assert abs(E1 - E0) / abs(E0) <= 1e-5
+    g.close()
+
+
+def test_error_paths():
+    note("error paths")
+    x, v, m = plummer(500, 1007)
+    g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g.init()
+    # force at a time other than the last prediction
+    with pytest.raises(NBodyError) as e:
+        g.force_jerk([0, 1], 2.0 ** -10)
+    assert e.value.code == _lib.NBODY_ESTATE
+    # t not a multiple of the tick
+    with pytest.raises(NBodyError) as e:
+        g.predict(1e-9)
+    assert e.value.code == _lib.NBODY_EINVAL
+    # out-of-range index: reported at the next synchronising call
+    g.predict(0.0)
+    g.force_jerk([0, 500, 3], 0.0)
+    with pytest.raises(NBodyError) as e:
+        g.sync()
+    assert e.value.code == _lib.NBODY_ERANGE
+    g.sync()  # cleared
+    # correcting a particle that is not due
+    _, _, _, _, tg, dtg = g.host_state()
+    t, act = _due(tg, dtg)
+    notdue = np.setdiff1d(np.arange(500), act)[:1].astype(np.int32)
+    g.predict(t)
+    acc, jerk, _ = g.force_jerk(notdue, t)
+    g.correct(notdue, t, acc, jerk)
+    with pytest.raises(NBodyError) as e:
+        g.sync()
+    assert e.value.code == _lib.NBODY_ESTATE
+    g.close()
+
+
+def test_nonfinite_state_is_reported():
+    note("non-finite")
+    x, v, m = plummer(300, 1008)
+    x = x.copy()
+    x[17, 1] = np.nan
+    g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    with pytest.raises(NBodyError) as e:
+        g.init()
+    assert e.value.code == _lib.NBODY_ENONFINITE
+    g.close()
+
+
+def test_runs_are_bitwise_deterministic():
+    note("determinism")
+    x, v, m = plummer(3000, 1009)
+    outs = []
+    for _ in range(2):
+        g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+        g.init()
+        g.run_until(1 / 64)
+        outs.append(g.host_state())
+        g.close()
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
