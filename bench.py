@@ -1,0 +1,265 @@
+#!/usr/bin/env python3
+"""Benchmark of the direct N-body hot path on one MI355X.
+
+Workload (the headline configuration): Plummer sphere, N = 196608 equal
+masses, eps = 1/1024, Aarseth eta = 0.01, block steps in [2^-20, 2^-3],
+mixed precision (FP32 pairwise terms, FP64 coordinates and accumulation).
+One step = one full force sweep (acceleration, jerk and potential of all N
+particles from all N at t = 0) followed by block steps (select, predict,
+force, correct) up to t = 1/8, starting from the same post-start-up state.
+The value is whole-step throughput in pairwise acc+jerk interactions per
+second (full sweep n*N plus every block step's n*N), with all state resident
+on the GPU.  The FP64 form of the same workload, the full-sweep kernel
+against the FP32 vector roofline, the oracle's CPU rate on a bounded sample,
+and the per-particle force error against the oracle are reported beside it.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "acc+jerk interactions/s, mixed vs FP64, N=196608, rel force err ≤1e-6"
+FLOPS_PER_INTERACTION = 60          # convention for acc+jerk
+PEAK_FP32 = 157.3e12                # MI355X FP32 vector, published
+PEAK_FP64 = 78.6e12                 # MI355X FP64 vector, published
+N_DEFAULT = 196608
+EPS = 1.0 / 1024
+T_END = 1.0 / 8
+SEED = 1003
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+class Run:
+    """One precision's system plus a snapshot of its post-start-up state."""
+
+    def __init__(self, x, v, m, precision, torch):
+        from paper_0709_4552_amd import NBody
+        self.torch = torch
+        self.g = NBody(x, v, m, EPS, eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3,
+                       precision=precision)
+        self.g.init()
+        g = self.g
+        # autotune every block-size class (outside any timed region)
+        self.tuning = []
+        for n_probe in sorted({g.n, min(g.n, 1024), min(g.n, 128), min(g.n, 16), 1}, reverse=True):
+            t, ms = g.autotune(n_probe)
+            t["n_probe"] = n_probe
+            t["ms"] = ms
+            self.tuning.append(t)
+            log(f"autotune n={n_probe}: class {t['size_class']} i_per_lane={t['i_per_lane']} "
+                f"j_lanes={t['j_lanes']} {ms:.3f} ms")
+        self.snap = [t.clone() for t in (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)]
+        self.all = torch.arange(g.n, dtype=torch.int32, device=g.dev)
+        self.stream = g.stream
+        self.ev0 = torch.cuda.Event(enable_timing=True)
+        self.ev1 = torch.cuda.Event(enable_timing=True)
+        self.sweep_ms = []
+        self.step_ms = []
+        self.inter = []
+
+    def restore(self):
+        g = self.g
+        for dst, src in zip((g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level), self.snap):
+            dst.copy_(src)
+
+    def step(self, timed: bool):
+        """Full sweep + block steps to T_END; returns interactions done."""
+        g, torch = self.g, self.torch
+        self.restore()
+        torch.cuda.synchronize()
+        st0 = g.stats()
+        s0 = st0["interactions"]
+        self._steps0 = st0["block_steps"]
+        t0 = time.perf_counter()
+        with torch.cuda.stream(self.stream):
+            g.predict(0.0)
+            self.ev0.record(self.stream)
+            acc, jerk, pot = g.force_jerk(self.all, 0.0, want_pot=True)
+            self.ev1.record(self.stream)
+        g.run_until(T_END)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st = g.stats()
+        inter = float(g.n) * g.n + (st["interactions"] - s0)
+        self.block_steps = st["block_steps"] - self._steps0 if hasattr(self, "_steps0") else None
+        if timed:
+            self.sweep_ms.append(self.ev0.elapsed_time(self.ev1))
+            self.step_ms.append((t1 - t0) * 1e3)
+            self.inter.append(inter)
+        self.last_sweep = (acc, jerk, pot)
+        return inter
+
+    def energy(self):
+        """Total energy at the current synchronised time, from the library's
+        own potential (one full sweep) and the state on the GPU."""
+        g, torch = self.g, self.torch
+        t = float(g.t_tick.max().item()) * 2.0 ** -20
+        g.predict(t)
+        _, _, pot = g.force_jerk(self.all, t, want_pot=True)
+        m = g.mass
+        ek = 0.5 * (m * (g.vel * g.vel).sum(0)).sum()
+        ep = 0.5 * (m * pot).sum()
+        return float((ek + ep).item())
+
+
+def cpu_baseline(x, v, m, sweep_acc, budget_s: float):
+    """Oracle force on a bounded random sample of i against all N (CPU, all
+    threads), and the GPU full-sweep error on that sample."""
+    import numpy as np
+
+    import oracle
+    n = x.shape[0]
+    rng = np.random.Generator(np.random.PCG64(7))
+    probe = rng.integers(0, n, 64)
+    t0 = time.perf_counter()
+    oracle.force(x, v, m, EPS, probe)
+    dt = time.perf_counter() - t0
+    per_i = dt / probe.size
+    k = int(min(n, max(256, budget_s / max(per_i, 1e-9))))
+    r = np.linalg.norm(x, axis=1)
+    # the sample: the most central particles (hardest cancellation) + random ones
+    sample = np.unique(np.concatenate([np.argsort(r)[:min(512, k // 4)],
+                                       rng.integers(0, n, k)]))[:k]
+    t0 = time.perf_counter()
+    ra, rj, rp = oracle.force(x, v, m, EPS, sample)
+    dt = time.perf_counter() - t0
+    rate = sample.size * float(n) / dt
+    out = {"value": rate, "unit": "interactions/s", "cores": oracle.threads(), "kind": "oracle",
+           "sample": f"oracle acc+jerk+pot of {sample.size} particles (the {min(512, k // 4)} most "
+                     f"central + random) against all N={n}, FP64, {dt:.1f} s"}
+    errs = {}
+    for name, (a, j) in sweep_acc.items():
+        ea = np.linalg.norm(a[sample] - ra, axis=1) / np.linalg.norm(ra, axis=1)
+        ej = np.linalg.norm(j[sample] - rj, axis=1) / np.linalg.norm(rj, axis=1)
+        errs[name] = {"max_rel_acc_err": float(ea.max()), "p999_rel_acc_err":
+                      float(np.quantile(ea, 0.999)), "median_rel_acc_err": float(np.median(ea)),
+                      "max_rel_jerk_err": float(ej.max()), "particles": int(sample.size)}
+    return out, errs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=N_DEFAULT, help="particles (default 196608)")
+    ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 steps (0 = skip)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-energy", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(how the path would shard is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from nbody_inputs import plummer
+    from paper_0709_4552_amd import NBODY_PREC_FP64, NBODY_PREC_MIXED
+
+    x, v, m = plummer(args.n, SEED)
+    log(f"workload: Plummer N={args.n} seed={SEED} eps=1/1024 to t={T_END}")
+
+    mixed = Run(x, v, m, NBODY_PREC_MIXED, torch)
+    for w in range(args.warmup):
+        mixed.step(False)
+        log(f"warmup {w + 1}/{args.warmup} done")
+    E0 = None
+    for k in range(args.steps):
+        mixed.step(True)
+        log(f"step {k + 1}/{args.steps}: {mixed.step_ms[-1]:.1f} ms, "
+            f"{mixed.inter[-1]:.3e} interactions, sweep {mixed.sweep_ms[-1]:.2f} ms")
+    acc_m = mixed.last_sweep[0].T.cpu().numpy()
+    jerk_m = mixed.last_sweep[1].T.cpu().numpy()
+    energy = None
+    if not args.no_energy:
+        mixed.restore()
+        E0 = mixed.energy()
+        mixed.g.run_until(T_END)
+        E1 = mixed.energy()
+        energy = {"dE_over_E_t0.125": (E1 - E0) / abs(E0), "E0": E0}
+        log(f"energy: dE/E = {(E1 - E0) / abs(E0):.3e}")
+
+    total_ms = sum(mixed.step_ms)
+    total_inter = sum(mixed.inter)
+    value = total_inter / (total_ms * 1e-3)
+    sweep_ms = sum(mixed.sweep_ms) / len(mixed.sweep_ms)
+    sweep_rate = float(args.n) * args.n / (sweep_ms * 1e-3)
+    achieved = FLOPS_PER_INTERACTION * sweep_rate
+
+    fp64 = None
+    acc64 = None
+    if args.fp64_steps > 0:
+        r64 = Run(x, v, m, NBODY_PREC_FP64, torch)
+        for k in range(args.fp64_steps):
+            r64.step(True)
+            log(f"fp64 step {k + 1}/{args.fp64_steps}: {r64.step_ms[-1]:.1f} ms")
+        s64 = sum(r64.sweep_ms) / len(r64.sweep_ms)
+        rate64 = float(args.n) * args.n / (s64 * 1e-3)
+        fp64 = {"value": sum(r64.inter) / (sum(r64.step_ms) * 1e-3), "unit": "interactions/s",
+                "ms_per_step": sum(r64.step_ms) / len(r64.step_ms),
+                "full_sweep_ms": s64, "full_sweep_interactions_per_s": rate64,
+                "full_sweep_frac_of_fp64_peak": FLOPS_PER_INTERACTION * rate64 / PEAK_FP64}
+        acc64 = (r64.last_sweep[0].T.cpu().numpy(), r64.last_sweep[1].T.cpu().numpy())
+        r64.g.close()
+
+    cpu = None
+    accuracy = None
+    if not args.no_cpu_baseline:
+        sw = {"mixed": (acc_m, jerk_m)}
+        if acc64 is not None:
+            sw["fp64"] = acc64
+        cpu, accuracy = cpu_baseline(x, v, m, sw, args.cpu_seconds)
+        log(f"cpu oracle: {cpu['value']:.3e} interactions/s on {cpu['cores']} threads")
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "interactions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 pairwise, f64 coordinates/accumulation",
+        "data": "synthetic",
+        "config": {"workload": f"plummer_N{args.n}_eps1/1024_eta0.01_fullsweep+blocksteps_to_t0.125",
+                   "n": args.n, "eps": EPS, "eta": 0.01, "dt_range": "[2^-20, 2^-3]",
+                   "t_end": T_END, "seed": SEED, "precision": "mixed",
+                   "interactions_per_step": total_inter / args.steps,
+                   "block_steps_per_step": mixed.block_steps,
+                   "autotuned_shapes": mixed.tuning},
+        "full_sweep": {"ms": sweep_ms, "interactions_per_s": sweep_rate},
+        "roofline": {"bound": "alu", "kernel": "k_force (mixed, n=N full sweep)",
+                     "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "flops_per_interaction": FLOPS_PER_INTERACTION},
+        "fp64": fp64,
+        "cpu_baseline": cpu,
+        "accuracy": accuracy,
+        "energy": energy,
+        "context": {"grape6af_interactions_per_s": 1.0 / 4.3e-10,
+                    "grape6af_simultaneous_interactions": 42},
+    }
+    mixed.g.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

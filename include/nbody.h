@@ -103,13 +103,18 @@ typedef struct {
 } nbody_params;
 
 /*
- * Launch shape of the force kernel (chosen by nbody_autotune or set by
- * hand).  i_per_lane in {1,2}; j_lanes in {1,4,16,64,256} is the number of
- * lanes that share one i-particle and split the j loop between them;
- * j_tile in {128,256} is the number of j-particles staged in LDS per round;
- * grid is the number of persistent workgroups (0 = library default).
+ * Launch shape of the force kernel for one block-size class (chosen by
+ * nbody_autotune or set by hand).  Blocks are sorted into NBODY_SIZE_CLASSES
+ * classes by their mean size n over the active clusters: class 0 for
+ * n >= 2048, 1 for n >= 256, 2 for n >= 32, 3 for n >= 4, 4 below.
+ * i_per_lane in {1,2} (2 only with j_lanes = 1); j_lanes in {1,4,16,64,256}
+ * is the number of lanes that share one i-particle and split its j loop;
+ * j_tile = 256 j-particles staged in LDS per round; grid is the number of
+ * persistent workgroups (0 = CUs x occupancy).
  */
+#define NBODY_SIZE_CLASSES 5
 typedef struct {
+    int32_t size_class;
     int32_t i_per_lane;
     int32_t j_lanes;
     int32_t j_tile;
@@ -228,16 +233,20 @@ int nbody_get_stats(nbody_ctx *ctx, nbody_stats *out);
  */
 int nbody_read_predicted(nbody_ctx *ctx, double *pos_dev, double *vel_dev);
 
-/* Read / set the force kernel's launch shape (EINVAL for an unsupported shape). */
+/* Read (out->size_class selects the class) / set the launch shape of one
+ * class; EINVAL for an unknown class or an unsupported shape. */
 int nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 int nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *tuning);
 
 /*
- * Time every supported launch shape of the force kernel on the current
- * state for a block of n_probe particles (1 <= n_probe <= largest cluster,
- * 0 = each cluster's full size) and keep the fastest.  Predicts to the
- * current time of cluster 0 first; does not change the particle state.
- * *best_ms (may be NULL) receives the best time per force call.
+ * Autotuner: for blocks of n_probe particles per cluster (1 <= n_probe; a
+ * cluster smaller than n_probe uses all its particles), time one force
+ * evaluation with every supported launch shape of the class that block size
+ * falls in, and keep the fastest for that class.  Runs on the j-particle
+ * buffer of the last prediction (valid after nbody_init) and writes only
+ * the context's scratch buffers: the particle state is not changed.
+ * Synchronises.  *best receives the chosen shape; *best_ms (may be NULL) the
+ * best time of one force evaluation in milliseconds.
  */
 int nbody_autotune(nbody_ctx *ctx, int64_t n_probe, nbody_tuning *best, double *best_ms);
 

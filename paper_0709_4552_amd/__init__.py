@@ -150,19 +150,23 @@ class NBody:
               "nbody_read_predicted")
         return pos, vel
 
-    def get_tuning(self):
-        rc, t = _lib.nbody_get_tuning(self.ctx)
+    def get_tuning(self, size_class: int = 0):
+        rc, t = _lib.nbody_get_tuning(self.ctx, size_class)
         check(rc, "nbody_get_tuning")
-        return t
+        return {"size_class": t.size_class, "i_per_lane": t.i_per_lane, "j_lanes": t.j_lanes,
+                "j_tile": t.j_tile, "grid": t.grid}
 
-    def set_tuning(self, i_per_lane: int, j_lanes: int, j_tile: int = 256, grid: int = 0):
-        t = _lib.nbody_tuning(i_per_lane, j_lanes, j_tile, grid)
+    def set_tuning(self, i_per_lane: int, j_lanes: int, j_tile: int = 256, grid: int = 0,
+                   size_class: int = 0):
+        t = _lib.nbody_tuning(size_class, i_per_lane, j_lanes, j_tile, grid)
         check(_lib.nbody_set_tuning(self.ctx, t), "nbody_set_tuning")
 
-    def autotune(self, n_probe: int = 0):
+    def autotune(self, n_probe: int):
+        """Pick the fastest launch shape for blocks of n_probe; returns (tuning, ms)."""
         rc, t, ms = _lib.nbody_autotune(self.ctx, n_probe)
         check(rc, "nbody_autotune")
-        return t, ms
+        return ({"size_class": t.size_class, "i_per_lane": t.i_per_lane, "j_lanes": t.j_lanes,
+                 "j_tile": t.j_tile, "grid": t.grid}, ms)
 
     # --- host views (copies) ------------------------------------------------
     def host_state(self):

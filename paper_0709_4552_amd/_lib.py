@@ -59,8 +59,12 @@ class nbody_params(ctypes.Structure):
     ]
 
 
+NBODY_SIZE_CLASSES = 5
+
+
 class nbody_tuning(ctypes.Structure):
     _fields_ = [
+        ("size_class", ctypes.c_int32),
         ("i_per_lane", ctypes.c_int32),
         ("j_lanes", ctypes.c_int32),
         ("j_tile", ctypes.c_int32),
@@ -194,8 +198,9 @@ def nbody_read_predicted(ctx: int, pos_ptr: int, vel_ptr: int) -> int:
                                        ctypes.c_void_p(vel_ptr))
 
 
-def nbody_get_tuning(ctx: int):
+def nbody_get_tuning(ctx: int, size_class: int = 0):
     t = nbody_tuning()
+    t.size_class = size_class
     rc = load().nbody_get_tuning(ctypes.c_void_p(ctx), ctypes.byref(t))
     return rc, t
 

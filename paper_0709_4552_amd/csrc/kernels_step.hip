@@ -228,6 +228,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
     __shared__ int s_best_S;
     const int t = threadIdx.x;
     const int C = pr.C;
+    if (t == 0)
+        ctl->s_max = 0;
     // pass 1: take the block sizes of this step; total work
     double w_local = 0.0;
     int64_t n_local = 0, act_local = 0;
@@ -280,32 +282,30 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
         }
     const int64_t ib_size = ct.ib[cls];
     const int64_t grid = ct.grid[cls];
-    // one cluster: choose S by the cost model
+    // one cluster: choose S by the cost model (every thread tries one S)
     if (C == 1) {
-        __shared__ int64_t cost[64];
-        if (t < 64) {
-            const int64_t n = pl.n_cur[0];
-            const int64_t Nc = off[1] - off[0];
-            const int64_t tiles = (Nc + j_tile - 1) / j_tile;
-            const int64_t nib = (n + ib_size - 1) / ib_size;
-            const int64_t S = t + 1;
-            int64_t cst = INT64_MAX;
-            if (S <= tiles && (S == 1 || S * n <= part_cap) && n > 0) {
-                const int64_t tps = (tiles + S - 1) / S;
-                const int64_t Seff = (tiles + tps - 1) / tps;
-                const int64_t waves = (nib * Seff + grid - 1) / grid;
-                cst = waves * (tps + 1);
-            }
-            cost[t] = cst;
+        const int64_t n = pl.n_cur[0];
+        const int64_t Nc = off[1] - off[0];
+        const int64_t tiles = (Nc + j_tile - 1) / j_tile;
+        const int64_t nib = (n + ib_size - 1) / ib_size;
+        const int64_t S = t + 1;
+        int64_t key = INT64_MAX;
+        if (n > 0 && S <= tiles && S <= kMaxSlices && (S == 1 || S * n <= part_cap)) {
+            const int64_t tps = (tiles + S - 1) / S;
+            const int64_t Seff = (tiles + tps - 1) / tps;
+            const int64_t waves = (nib * Seff + grid - 1) / grid;
+            // time ~ waves of items x (tiles per slice + item overhead); ties -> smaller S
+            key = ((waves * (tps + 1)) << 11) | (S - 1);
         }
+        tmp[t] = key;
         __syncthreads();
-        if (t == 0) {
-            int best = 0;
-            for (int q = 1; q < 64; q++)
-                if (cost[q] < cost[best])
-                    best = q;
-            s_best_S = best + 1;
+        for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
+            if (t < o && tmp[t + o] < tmp[t])
+                tmp[t] = tmp[t + o];
+            __syncthreads();
         }
+        if (t == 0)
+            s_best_S = tmp[0] == INT64_MAX ? 1 : (int)(tmp[0] & 2047) + 1;
         __syncthreads();
     }
     if (t == 0)
@@ -346,6 +346,8 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
                 }
                 pl.S[c] = S;
                 pl.jlen[c] = jl;
+                if (S > 1)
+                    atomicMax(&ctl->s_max, S);
             }
             int64_t tot_i, tot_p;
             const int64_t ex_i = block_exclusive_scan(items, tmp, &tot_i);
@@ -387,12 +389,53 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
 }
 
 // ---------------------------------------------------------------- reduction
-// Sums the per-slice partial results in slice order (deterministic).
+// Sums the per-slice partial results of every slot whose cluster was split
+// into S > 1 j-slices.  Narrow splits (S <= 8): one thread per slot, slices in
+// order.  Wide splits: one wave per slot, lane l adds slices l, l+64, ...,
+// then a fixed butterfly.  Both orders are fixed, so results are bitwise
+// reproducible.  With one cluster only the n live slots are visited.
 __global__ __launch_bounds__(kWG) void k_reduce(ForceArgs fa, const int32_t *cid,
-                                                int64_t slot_space) {
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < slot_space;
-         s += (int64_t)gridDim.x * blockDim.x) {
-        const int c = fa.C > 1 ? cid[s] : 0;
+                                                int64_t slot_space, const int32_t *s_max) {
+    const int smax = uniform_i32(*s_max);
+    if (smax <= 1)
+        return;
+    int64_t bound = slot_space;
+    if (fa.C == 1)
+        bound = min(bound, (int64_t)uniform_i32(fa.n_cur[0]));
+    if (smax <= 8) {
+        for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < bound;
+             s += (int64_t)gridDim.x * blockDim.x) {
+            const int c = fa.C > 1 ? cid[s] : 0;
+            const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
+            const int64_t n = fa.n_cur[c];
+            const int S = fa.S[c];
+            if (k >= n || S <= 1)
+                continue;
+            const int64_t base = fa.part_begin[c] + k;
+            double acc[7];
+#pragma unroll
+            for (int q = 0; q < 7; q++) {
+                double sum = 0.0;
+                for (int js = 0; js < S; js++)
+                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+                acc[q] = sum;
+            }
+            fa.out_acc[s] = acc[0];
+            fa.out_acc[fa.out_stride + s] = acc[1];
+            fa.out_acc[2 * fa.out_stride + s] = acc[2];
+            fa.out_jerk[s] = acc[3];
+            fa.out_jerk[fa.out_stride + s] = acc[4];
+            fa.out_jerk[2 * fa.out_stride + s] = acc[5];
+            if (fa.out_pot)
+                fa.out_pot[s] = acc[6];
+        }
+        return;
+    }
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t s = wave; s < bound; s += nwaves) {
+        const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
         const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
         const int64_t n = fa.n_cur[c];
         const int S = fa.S[c];
@@ -403,18 +446,23 @@ __global__ __launch_bounds__(kWG) void k_reduce(ForceArgs fa, const int32_t *cid
 #pragma unroll
         for (int q = 0; q < 7; q++) {
             double sum = 0.0;
-            for (int js = 0; js < S; js++)
+            for (int js = lane; js < S; js += 64)
                 sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+                sum += __shfl_xor(sum, o);
             acc[q] = sum;
         }
-        fa.out_acc[s] = acc[0];
-        fa.out_acc[fa.out_stride + s] = acc[1];
-        fa.out_acc[2 * fa.out_stride + s] = acc[2];
-        fa.out_jerk[s] = acc[3];
-        fa.out_jerk[fa.out_stride + s] = acc[4];
-        fa.out_jerk[2 * fa.out_stride + s] = acc[5];
-        if (fa.out_pot)
-            fa.out_pot[s] = acc[6];
+        if (lane == 0) {
+            fa.out_acc[s] = acc[0];
+            fa.out_acc[fa.out_stride + s] = acc[1];
+            fa.out_acc[2 * fa.out_stride + s] = acc[2];
+            fa.out_jerk[s] = acc[3];
+            fa.out_jerk[fa.out_stride + s] = acc[4];
+            fa.out_jerk[2 * fa.out_stride + s] = acc[5];
+            if (fa.out_pot)
+                fa.out_pot[s] = acc[6];
+        }
     }
 }
 
@@ -428,7 +476,8 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
                                                  int64_t in_stride, DevCtl *ctl) {
     unsigned long long clamps = 0;
     int32_t err = 0;
-    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < slot_space;
+    const int64_t bound = pr.C == 1 ? min(slot_space, (int64_t)n_cur[0]) : slot_space;
+    for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < bound;
          s += (int64_t)gridDim.x * blockDim.x) {
         const int c = pr.C > 1 ? cid[s] : 0;
         const int64_t cb = off[c];
@@ -622,9 +671,10 @@ hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, 
 }
 
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce, dim3(grid_for(slot_space)), dim3(kWG), 0, s, fa, cid,
-                       slot_space);
+                         const int32_t *s_max, hipStream_t s) {
+    // enough waves for one per slot up to 4096 workgroups; grid-stride beyond
+    hipLaunchKernelGGL(k_reduce, dim3(grid_for(slot_space * 64)), dim3(kWG), 0, s, fa, cid,
+                       slot_space, s_max);
     return hipGetLastError();
 }
 

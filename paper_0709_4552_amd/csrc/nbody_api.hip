@@ -194,7 +194,7 @@ hipError_t enqueue_force(nbody_ctx *c, const int32_t *i_list, int slots_at_offse
         if (e != hipSuccess)
             return e;
     }
-    return launch_reduce(fa, c->cid_d, slot_space, c->stream);
+    return launch_reduce(fa, c->cid_d, slot_space, &c->ctl->s_max, c->stream);
 }
 
 int read_ctl(nbody_ctx *c, DevCtl *out) {
@@ -241,7 +241,7 @@ hipError_t enqueue_block_step(nbody_ctx *c) {
         if (e != hipSuccess)
             return e;
     }
-    e = launch_reduce(fa, c->cid_d, c->pr.n_total, c->stream);
+    e = launch_reduce(fa, c->cid_d, c->pr.n_total, &c->ctl->s_max, c->stream);
     if (e != hipSuccess)
         return e;
     return launch_correct(c->st, c->pr, c->i_list_d, 1, c->off_d, c->cid_d, c->pl.n_cur,
@@ -377,7 +377,7 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
     st.lev = s->level;
 
     // default launch shapes by block size
-    const Shape shapes[kClasses] = {{2, 1, kJTile}, {1, 4, kJTile}, {1, 16, kJTile},
+    const Shape shapes[kClasses] = {{1, 1, kJTile}, {1, 4, kJTile}, {1, 16, kJTile},
                                     {1, 64, kJTile}, {1, 256, kJTile}};
     const int32_t min_n[kClasses] = {2048, 256, 32, 4, 0};
     for (int k = 0; k < kClasses; k++) {
@@ -682,34 +682,125 @@ int nbody_read_predicted(nbody_ctx *c, double *pos, double *vel) {
 }
 
 int nbody_get_tuning(const nbody_ctx *c, nbody_tuning *out) {
-    if (!c || !out)
+    if (!c || !out || out->size_class < 0 || out->size_class >= kClasses)
         return NBODY_EINVAL;
-    out->i_per_lane = c->cls_shape[0].i_per_lane;
-    out->j_lanes = c->cls_shape[0].j_lanes;
-    out->j_tile = c->cls_shape[0].j_tile;
-    out->grid = c->cls_grid[0];
+    const int k = out->size_class;
+    out->i_per_lane = c->cls_shape[k].i_per_lane;
+    out->j_lanes = c->cls_shape[k].j_lanes;
+    out->j_tile = c->cls_shape[k].j_tile;
+    out->grid = c->cls_grid[k];
     return NBODY_OK;
 }
 
 int nbody_set_tuning(nbody_ctx *c, const nbody_tuning *t) {
-    if (!c || !t)
+    if (!c || !t || t->size_class < 0 || t->size_class >= kClasses)
         return NBODY_EINVAL;
     const Shape sh{t->i_per_lane, t->j_lanes, t->j_tile};
     if (!force_shape_supported(sh) || t->grid < 0)
         return NBODY_EINVAL;
-    c->cls_shape[0] = sh;
-    c->cls_grid[0] = t->grid;
-    std::memset(c->occ_cache[0], 0, sizeof(c->occ_cache[0]));
+    const int k = t->size_class;
+    c->cls_shape[k] = sh;
+    c->cls_grid[k] = t->grid;
+    std::memset(c->occ_cache[k], 0, sizeof(c->occ_cache[k]));
     drop_graph(c);
     return NBODY_OK;
 }
 
 int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *best_ms) {
-    (void)c;
-    (void)n_probe;
-    (void)best;
-    (void)best_ms;
-    return NBODY_EUNSUPPORTED;
+    if (!c || !best || n_probe < 1 || n_probe > c->max_cluster)
+        return NBODY_EINVAL;
+    if (!c->initialised)
+        return NBODY_ESTATE;
+    const int64_t N = c->pr.n_total;
+    // per-cluster block sizes and their mean over clusters
+    std::vector<int32_t> nc(c->pr.C);
+    int64_t sum = 0;
+    for (int k = 0; k < c->pr.C; k++) {
+        nc[k] = (int32_t)std::min<int64_t>(n_probe, c->off_h[k + 1] - c->off_h[k]);
+        sum += nc[k];
+    }
+    const int cls = class_of(c, sum / c->pr.C);
+    static const Shape cand[] = {{1, 1, 256}, {2, 1, 256}, {1, 4, 256}, {1, 16, 256},
+                                 {1, 64, 256}, {1, 256, 256}};
+    const Shape keep = c->cls_shape[cls];
+    const int keep_grid = c->cls_grid[cls];
+    hipEvent_t e0, e1;
+    NB_TRY(hipEventCreate(&e0));
+    NB_TRY(hipEventCreate(&e1));
+    double best_t = 1e300;
+    Shape best_s = keep;
+    int rc = NBODY_OK;
+    for (const Shape &sh : cand) {
+        c->cls_shape[cls] = sh;
+        c->cls_grid[cls] = 0;
+        std::memset(c->occ_cache[cls], 0, sizeof(c->occ_cache[cls]));
+        float ms_min = 1e30f;
+        for (int rep = 0; rep < 3 && rc == NBODY_OK; rep++) {
+            hipError_t e = hipSuccess;
+            if (c->pr.C == 1) {
+                e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess)
+                    e = enqueue_force(c, c->iota_d, 0, nc[0], 0, 0, c->acc_new, c->jerk_new,
+                                      nullptr, N, nc[0]);
+            } else {
+                e = hipMemcpyAsync(c->n_act_d, nc.data(), nc.size() * sizeof(int32_t),
+                                   hipMemcpyHostToDevice, c->stream);
+                if (e == hipSuccess)
+                    e = launch_fill_i64(c->t_next_d, 0, c->pr.C, c->stream);
+                if (e == hipSuccess)
+                    e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess)
+                    e = enqueue_force(c, c->iota_d, 1, -1, 0, 0, c->acc_new, c->jerk_new,
+                                      nullptr, N, N);
+            }
+            if (e == hipSuccess)
+                e = hipEventRecord(e1, c->stream);
+            if (e == hipSuccess)
+                e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess)
+                e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) {
+                rc = map_err(e);
+                break;
+            }
+            if (rep > 0)  // the first call warms caches and code
+                ms_min = std::min(ms_min, ms);
+        }
+        if (rc != NBODY_OK)
+            break;
+        if (ms_min < best_t) {
+            best_t = ms_min;
+            best_s = sh;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    // the device plan arrays were used as scratch; leave no pending block
+    (void)launch_fill_i32(c->n_act_d, 0, c->pr.C, c->stream);
+    (void)launch_fill_i64(c->t_next_d, LLONG_MAX, c->pr.C, c->stream);
+    if (rc != NBODY_OK) {
+        c->cls_shape[cls] = keep;
+        c->cls_grid[cls] = keep_grid;
+        std::memset(c->occ_cache[cls], 0, sizeof(c->occ_cache[cls]));
+        return rc;
+    }
+    c->cls_shape[cls] = best_s;
+    c->cls_grid[cls] = 0;
+    std::memset(c->occ_cache[cls], 0, sizeof(c->occ_cache[cls]));
+    drop_graph(c);
+    best->size_class = cls;
+    best->i_per_lane = best_s.i_per_lane;
+    best->j_lanes = best_s.j_lanes;
+    best->j_tile = best_s.j_tile;
+    best->grid = 0;
+    if (best_ms)
+        *best_ms = best_t;
+    DevCtl h;
+    rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    return consume_error(c, h);
 }
 
 }  // extern "C"

@@ -35,7 +35,11 @@ struct DevCtl {
     int32_t any_active;            // at least one cluster active in the last plan
     int32_t cls;                   // shape class chosen by the last plan
     unsigned long long item_counter;  // work queue head of the force kernel
+    int32_t s_max;                 // largest j-split of the current plan (0 = none)
+    int32_t pad2;
 };
+
+constexpr int kMaxSlices = 1024;   // j-slices per cluster the planner may choose
 
 // Launch-shape classes by block size: class k is used when the mean block
 // size of the active clusters is >= min_n[k] (classes in decreasing order).
@@ -169,7 +173,7 @@ hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, 
                        int32_t j_tile, int32_t host_n, int64_t host_t, int32_t count_stats,
                        hipStream_t s);
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
-                         hipStream_t s);
+                         const int32_t *s_max, hipStream_t s);
 hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_list,
                           int32_t slots_at_offsets, const int64_t *off, const int32_t *cid,
                           const int32_t *n_cur, const int64_t *t_cur, int64_t slot_space,

@@ -33,7 +33,7 @@ def test_struct_layouts_match_header():
     # nbody_state: 15 pointers; nbody_params: int64, int32(+pad), ptr, 3 doubles, 3 int32 (+pad)
     assert ctypes.sizeof(_lib.nbody_state) == 15 * 8
     assert ctypes.sizeof(_lib.nbody_params) == 8 + 8 + 8 + 24 + 16
-    assert ctypes.sizeof(_lib.nbody_tuning) == 16
+    assert ctypes.sizeof(_lib.nbody_tuning) == 20
     assert ctypes.sizeof(_lib.nbody_stats) == 32
 
 

@@ -215,9 +215,9 @@ def test_ensemble_matches_independent_oracles(prec):
     note(f"ensemble 6 clusters prec={prec}")
     x, v, m, offs = ensemble(6, 77, 100, 700)
     eps = 1 / 256
-    T = 1 / 16
-    prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-3)
-    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec,
+    T = 1 / 16  # a multiple of the largest step: every particle ends at T
+    prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-4)
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-4, precision=prec,
               cluster_offset=offs)
     g.init()
     g.run_until(T)
@@ -292,3 +292,25 @@ def test_runs_are_bitwise_deterministic():
         g.close()
     for a, b in zip(outs[0], outs[1]):
         assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_autotune_keeps_results(prec):
+    note(f"autotune prec={prec}")
+    N = 2500
+    x, v, m = plummer(N, 1010)
+    eps = 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    for n_probe in (N, 300, 40, 5, 1):
+        t, ms = g.autotune(n_probe)
+        assert 0 <= t["size_class"] < 5 and ms > 0
+        assert t == {**g.get_tuning(t["size_class"]), "size_class": t["size_class"]}
+    g.predict(0.0)
+    for n in (N, 300, 40, 5, 1):
+        il = np.arange(n, dtype=np.int32)
+        acc, jerk, pot = g.force_jerk(il, 0.0)
+        ra, rj, rp = oracle.force(x, v, m, eps, il)
+        assert relerr(acc.T.cpu().numpy(), ra).max() <= TOL[prec]["a"]
+        assert relerr(pot.cpu().numpy(), rp).max() <= TOL[prec]["p"]
+    g.close()
