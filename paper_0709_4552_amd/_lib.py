@@ -10,7 +10,7 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libnbody.so")
+LIB_PATH = os.environ.get("NBODY_LIB") or os.path.join(HERE, "libnbody.so")
 
 NBODY_OK = 0
 NBODY_EINVAL = -1

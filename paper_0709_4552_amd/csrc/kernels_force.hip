@@ -235,49 +235,75 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
             if (MIXED) {
 #pragma unroll
                 for (int ch = 0; ch < NCH; ch++) {
-#pragma unroll 4
-                    for (int u = 0; u < CHJ; u++) {
-                        const int t = lj + (ch * CHJ + u) * LJ;
-                        const float4 p = sP[t];
-                        const float4 q = sQ[t];
-                        const float2 r = sR[t];
+                    // groups of G j: all LDS reads first, then the arithmetic, then one
+                    // wave-uniform test for near pairs (recorded in a rare branch).
+                    // G = 2 keeps the kernel near 94 VGPRs (5 waves per SIMD); larger
+                    // groups cost occupancy and measured slower on gfx950.
+                    constexpr int G = CHJ < 2 ? CHJ : 2;
+#pragma unroll 1
+                    for (int u = 0; u < CHJ; u += G) {
+                        float4 p[G], q[G];
+                        float2 r[G];
 #pragma unroll
-                        for (int ii = 0; ii < I; ii++) {
-                            const float dx = (p.x - xh[ii]) + (q.x - xl[ii]);
-                            const float dy = (p.y - yh[ii]) + (q.y - yl[ii]);
-                            const float dz = (p.z - zh[ii]) + (q.z - zl[ii]);
-                            const float wx = q.w - vxi[ii];
-                            const float wy = r.x - vyi[ii];
-                            const float wz = r.y - vzi[ii];
-                            const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, fa.eps2f)));
-                            const float rw = __builtin_fmaf(dz, wz, __builtin_fmaf(dy, wy, dx * wx));
-                            const bool near = s < sc_eff[ii];
-                            float rinv = __builtin_amdgcn_rsqf(s);
-                            if (EXCL)
-                                rinv = s > 0.f ? rinv : 0.f;
-                            rinv = near ? 0.f : rinv;
-                            const float rinv2 = rinv * rinv;
-                            const float mr = p.w * rinv;
-                            const float mr3 = mr * rinv2;
-                            const float al = rw * rinv2;
-                            const float be = mr3 * al;
-                            if (POT)
-                                fp[ii] += mr;
-                            fax[ii] = __builtin_fmaf(mr3, dx, fax[ii]);
-                            fay[ii] = __builtin_fmaf(mr3, dy, fay[ii]);
-                            faz[ii] = __builtin_fmaf(mr3, dz, faz[ii]);
-                            f1x[ii] = __builtin_fmaf(mr3, wx, f1x[ii]);
-                            f1y[ii] = __builtin_fmaf(mr3, wy, f1y[ii]);
-                            f1z[ii] = __builtin_fmaf(mr3, wz, f1z[ii]);
-                            f2x[ii] = __builtin_fmaf(be, dx, f2x[ii]);
-                            f2y[ii] = __builtin_fmaf(be, dy, f2y[ii]);
-                            f2z[ii] = __builtin_fmaf(be, dz, f2z[ii]);
-                            if (near) {
-                                // rare: remember the pair for the FP64 pass below;
-                                // a full list stops masking for the rest of the tile
-                                sNear[(ii * kNearCap + ncnt[ii]) * kWG + tid] = (uint8_t)t;
-                                if (++ncnt[ii] == kNearCap)
-                                    sc_eff[ii] = 0.f;
+                        for (int g = 0; g < G; g++) {
+                            const int t = lj + (ch * CHJ + u + g) * LJ;
+                            p[g] = sP[t];
+                            q[g] = sQ[t];
+                            r[g] = sR[t];
+                        }
+                        bool nr[G][I];
+                        bool any = false;
+#pragma unroll
+                        for (int g = 0; g < G; g++) {
+#pragma unroll
+                            for (int ii = 0; ii < I; ii++) {
+                                const float dx = (p[g].x - xh[ii]) + (q[g].x - xl[ii]);
+                                const float dy = (p[g].y - yh[ii]) + (q[g].y - yl[ii]);
+                                const float dz = (p[g].z - zh[ii]) + (q[g].z - zl[ii]);
+                                const float wx = q[g].w - vxi[ii];
+                                const float wy = r[g].x - vyi[ii];
+                                const float wz = r[g].y - vzi[ii];
+                                const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, fa.eps2f)));
+                                const float rw = __builtin_fmaf(dz, wz, __builtin_fmaf(dy, wy, dx * wx));
+                                const bool near = s < sc_eff[ii];
+                                nr[g][ii] = near;
+                                any = any || near;
+                                float rinv = __builtin_amdgcn_rsqf(s);
+                                if (EXCL)
+                                    rinv = s > 0.f ? rinv : 0.f;
+                                rinv = near ? 0.f : rinv;
+                                const float rinv2 = rinv * rinv;
+                                const float mr = p[g].w * rinv;
+                                const float mr3 = mr * rinv2;
+                                const float al = rw * rinv2;
+                                const float be = mr3 * al;
+                                if (POT)
+                                    fp[ii] += mr;
+                                fax[ii] = __builtin_fmaf(mr3, dx, fax[ii]);
+                                fay[ii] = __builtin_fmaf(mr3, dy, fay[ii]);
+                                faz[ii] = __builtin_fmaf(mr3, dz, faz[ii]);
+                                f1x[ii] = __builtin_fmaf(mr3, wx, f1x[ii]);
+                                f1y[ii] = __builtin_fmaf(mr3, wy, f1y[ii]);
+                                f1z[ii] = __builtin_fmaf(mr3, wz, f1z[ii]);
+                                f2x[ii] = __builtin_fmaf(be, dx, f2x[ii]);
+                                f2y[ii] = __builtin_fmaf(be, dy, f2y[ii]);
+                                f2z[ii] = __builtin_fmaf(be, dz, f2z[ii]);
+                            }
+                        }
+                        if (__ballot(any) != 0ull) {
+                            // rare: remember the pairs for the FP64 pass after the tile;
+                            // a full list stops masking for the rest of the tile
+#pragma unroll
+                            for (int g = 0; g < G; g++) {
+#pragma unroll
+                                for (int ii = 0; ii < I; ii++) {
+                                    if (nr[g][ii] && ncnt[ii] < kNearCap) {
+                                        const int t = lj + (ch * CHJ + u + g) * LJ;
+                                        sNear[(ii * kNearCap + ncnt[ii]) * kWG + tid] = (uint8_t)t;
+                                        if (++ncnt[ii] == kNearCap)
+                                            sc_eff[ii] = 0.f;
+                                    }
+                                }
                             }
                         }
                     }

@@ -388,6 +388,86 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
     }
 }
 
+// One cluster: the same plan computed by a single wave without barriers.
+// Lane l evaluates j-split counts S = l+1, l+65, ... (up to kMaxSlices) with
+// the cost model above; a wave minimum picks the best (ties -> smaller S).
+__global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, PlanDev pl,
+                                                 int32_t *n_act, int64_t *t_next, DevCtl *ctl,
+                                                 int64_t part_cap, ClassTable ct, int32_t j_tile,
+                                                 int32_t host_n, int64_t host_t,
+                                                 int32_t count_stats) {
+    const int lane = threadIdx.x;
+    int64_t n;
+    int64_t tcur;
+    if (host_n >= 0) {
+        n = host_n;
+        tcur = host_t;
+    } else {
+        n = uniform_i32(n_act[0]);
+        tcur = uniform_i64(t_next[0]);
+    }
+    const int64_t Nc = off[1] - off[0];
+    int cls = kClasses - 1;
+    for (int k = 0; k < kClasses; k++)
+        if (n >= ct.min_n[k]) {
+            cls = k;
+            break;
+        }
+    const int64_t ib_size = ct.ib[cls];
+    const int64_t grid = ct.grid[cls];
+    const int64_t tiles = (Nc + j_tile - 1) / j_tile;
+    const int64_t nib = (n + ib_size - 1) / ib_size;
+    int64_t key = INT64_MAX;
+    for (int64_t S = lane + 1; S <= kMaxSlices && S <= tiles; S += 64) {
+        if (n <= 0 || (S > 1 && S * n > part_cap))
+            continue;
+        const int64_t tps = (tiles + S - 1) / S;
+        const int64_t Seff = (tiles + tps - 1) / tps;
+        const int64_t waves = (nib * Seff + grid - 1) / grid;
+        const int64_t k2 = ((waves * (tps + 1)) << 11) | (S - 1);
+        key = k2 < key ? k2 : key;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t other = __shfl_xor(key, o);
+        key = other < key ? other : key;
+    }
+    if (lane != 0)
+        return;
+    int64_t S = key == INT64_MAX ? 1 : (key & 2047) + 1;
+    int64_t items = 0, parts = 0;
+    int32_t jl = 0, Sfin = 0;
+    if (n > 0 && Nc > 0) {
+        const int64_t tiles_per = (tiles + S - 1) / S;
+        jl = (int32_t)(tiles_per * j_tile);
+        Sfin = (int32_t)((Nc + jl - 1) / jl);
+        items = nib * Sfin;
+        parts = Sfin > 1 ? (int64_t)Sfin * n : 0;
+    }
+    if (host_n < 0) {
+        n_act[0] = 0;
+        t_next[0] = LLONG_MAX;
+    }
+    pl.n_cur[0] = (int32_t)n;
+    pl.t_cur[0] = tcur;
+    pl.S[0] = Sfin;
+    pl.jlen[0] = jl;
+    pl.item_begin[0] = 0;
+    pl.item_begin[1] = items;
+    pl.part_begin[0] = 0;
+    ctl->total_items = items;
+    ctl->part_used = parts;
+    ctl->item_counter = 0;
+    ctl->cls = cls;
+    ctl->s_max = Sfin > 1 ? Sfin : 0;
+    ctl->n_last = (int32_t)n;
+    ctl->any_active = n > 0;
+    if (count_stats) {
+        ctl->steps += n > 0 ? 1ull : 0ull;
+        ctl->updates += (unsigned long long)n;
+        ctl->interactions += (double)n * (double)Nc;
+    }
+}
+
 // ---------------------------------------------------------------- reduction
 // Sums the per-slice partial results of every slot whose cluster was split
 // into S > 1 j-slices.  Narrow splits (S <= 8): one thread per slot, slices in
@@ -665,8 +745,12 @@ hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, 
                        int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
                        int32_t j_tile, int32_t host_n, int64_t host_t, int32_t count_stats,
                        hipStream_t s) {
-    hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, pr, off, pl, n_act, t_next, ctl,
-                       part_cap, ct, j_tile, host_n, host_t, count_stats);
+    if (pr.C == 1)
+        hipLaunchKernelGGL(k_plan_one, dim3(1), dim3(64), 0, s, pr, off, pl, n_act, t_next, ctl,
+                           part_cap, ct, j_tile, host_n, host_t, count_stats);
+    else
+        hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, pr, off, pl, n_act, t_next,
+                           ctl, part_cap, ct, j_tile, host_n, host_t, count_stats);
     return hipGetLastError();
 }
 
