@@ -86,7 +86,7 @@ class Run:
         with torch.cuda.stream(self.stream):
             g.predict(0.0)
             self.ev0.record(self.stream)
-            acc, jerk, pot = g.force_jerk(self.all, 0.0, want_pot=False)
+            acc, jerk, pot = g.force_jerk(self.all, 0.0, want_pot=True)
             self.ev1.record(self.stream)
         g.run_until(T_END)
         torch.cuda.synchronize()
@@ -101,16 +101,17 @@ class Run:
         self.last_sweep = (acc, jerk, pot)
         return inter
 
-    def sweep_with_potential_ms(self, reps: int = 2) -> float:
-        """Time of the full sweep that also returns the potential (untimed in steps)."""
+    def sweep_without_potential_ms(self, reps: int = 2) -> float:
+        """Time of the full sweep returning acceleration and jerk only (the
+        kernel instance the block steps use)."""
         g, torch = self.g, self.torch
         self.restore()
         with torch.cuda.stream(self.stream):
             g.predict(0.0)
-            g.force_jerk(self.all, 0.0, want_pot=True)
+            g.force_jerk(self.all, 0.0, want_pot=False)
             self.ev0.record(self.stream)
             for _ in range(reps):
-                g.force_jerk(self.all, 0.0, want_pot=True)
+                g.force_jerk(self.all, 0.0, want_pot=False)
             self.ev1.record(self.stream)
         torch.cuda.synchronize()
         return self.ev0.elapsed_time(self.ev1) / reps
@@ -163,6 +164,152 @@ def cpu_baseline(x, v, m, sweep_acc, budget_s: float):
     return out, errs
 
 
+def blocksize_sweep(torch, n_big: int, cpu_check: bool):
+    """Force-only rates at N = n_big (eps = 1/4096, mixed) for block sizes
+    1, 64, 4096, 65536 and N; fixed-seed samples of i (seed 1006)."""
+    import numpy as np
+
+    from nbody_inputs import plummer
+    from paper_0709_4552_amd import NBODY_PREC_MIXED, NBody
+    x, v, m = plummer(n_big, 1005)
+    g = NBody(x, v, m, 1.0 / 4096, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g.init()
+    for n_probe in (65536, 4096, 128, 16, 1):
+        g.autotune(min(n_probe, n_big))
+    g.predict(0.0)
+    rng = np.random.Generator(np.random.PCG64(1006))
+    out = []
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    for n in (1, 64, 4096, 65536, n_big):
+        n = min(n, n_big)
+        il = np.arange(n_big, dtype=np.int32) if n == n_big else \
+            rng.choice(n_big, n, replace=False).astype(np.int32)
+        ilt = torch.as_tensor(il, device=g.dev)
+        reps = 3 if n < n_big else 1
+        with torch.cuda.stream(g.stream):
+            g.force_jerk(ilt, 0.0, want_pot=False)
+            ev0.record(g.stream)
+            for _ in range(reps):
+                acc, jerk, _ = g.force_jerk(ilt, 0.0, want_pot=False)
+            ev1.record(g.stream)
+        torch.cuda.synchronize()
+        ms = ev0.elapsed_time(ev1) / reps
+        rate = float(n) * n_big / (ms * 1e-3)
+        rec = {"n_active": n, "ms": ms, "interactions_per_s": rate,
+               "frac_fp32_peak": FLOPS_PER_INTERACTION * rate / PEAK_FP32,
+               "jbuffer_GBps": 40.0 * n_big / (ms * 1e-3) / 1e9}
+        if cpu_check and n <= 4096:
+            import oracle
+            k = min(n, 512)
+            ra, _, _ = oracle.force(x, v, m, 1.0 / 4096, il[:k])
+            a = acc.T[:k].cpu().numpy()
+            rec["max_rel_acc_err"] = float((np.linalg.norm(a - ra, axis=1) /
+                                            np.linalg.norm(ra, axis=1)).max())
+            rec["checked_particles"] = k
+        out.append(rec)
+        log(f"N={n_big} n={n}: {ms:.3f} ms {rate:.3e} int/s")
+    g.close()
+    return {"workload": f"plummer_N{n_big}_eps1/4096_mixed_force_only", "points": out}
+
+
+def ensemble_bench(torch, n_clusters: int, t_short: float, t_full: float, per_cluster: bool):
+    """256 independent clusters (sizes log-uniform in [256, 8192], seed 1004),
+    eps = 1/256, eta = 0.01: one graph-replayed launch sequence per ensemble
+    step, against the same clusters run one after another."""
+    import numpy as np
+
+    import oracle
+    from nbody_inputs import ensemble
+    from paper_0709_4552_amd import NBODY_PREC_MIXED, NBody
+    x, v, m, offs = ensemble(n_clusters, 1004)
+    eps = 1.0 / 256
+    kw = dict(eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g = NBody(x, v, m, eps, cluster_offset=offs, **kw)
+    g.init()
+    tuning = [g.autotune(n)[0] for n in (2048, 512, 64, 8, 1)]
+    snap = [t.clone() for t in (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)]
+    torch.cuda.synchronize()
+    s0 = g.stats()
+    t0 = time.perf_counter()
+    steps = g.run_until(t_short)
+    torch.cuda.synchronize()
+    t_ens = time.perf_counter() - t0
+    s1 = g.stats()
+    inter_short = s1["interactions"] - s0["interactions"]
+    res = {"workload": f"ensemble_{n_clusters}_clusters_N256-8192_eps1/256_mixed",
+           "n_total": int(offs[-1]), "clusters": n_clusters, "autotuned_shapes": tuning,
+           "short": {"t_end": t_short, "ensemble_s": t_ens, "ensemble_steps": steps,
+                     "interactions": inter_short,
+                     "ensemble_interactions_per_s": inter_short / t_ens}}
+    log(f"ensemble to t={t_short}: {t_ens:.3f} s, {inter_short / t_ens:.3e} int/s")
+    if per_cluster:
+        tot = 0.0
+        inter_pc = 0.0
+        for k in range(n_clusters):
+            sl = slice(int(offs[k]), int(offs[k + 1]))
+            gk = NBody(x[sl], v[sl], m[sl], eps, **kw)
+            gk.init()
+            for (n_probe, t) in zip((2048, 512, 64, 8, 1), tuning):
+                gk.set_tuning(t["i_per_lane"], t["j_lanes"], size_class=t["size_class"])
+            torch.cuda.synchronize()
+            a0 = gk.stats()["interactions"]
+            t0 = time.perf_counter()
+            gk.run_until(t_short)
+            torch.cuda.synchronize()
+            tot += time.perf_counter() - t0
+            inter_pc += gk.stats()["interactions"] - a0
+            gk.close()
+        res["short"].update({"per_cluster_s": tot, "per_cluster_interactions_per_s": inter_pc / tot,
+                             "speedup_vs_per_cluster": tot / t_ens})
+        log(f"per-cluster to t={t_short}: {tot:.3f} s ({tot / t_ens:.1f}x slower)")
+    if t_full:
+        for dst, src in zip((g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level), snap):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        s0 = g.stats()
+        t0 = time.perf_counter()
+        steps = g.run_until(t_full)
+        torch.cuda.synchronize()
+        t_f = time.perf_counter() - t0
+        s1 = g.stats()
+        xg, vg, _, _, tg, _ = g.host_state()
+        dE = []
+        for k in range(n_clusters):
+            sl = slice(int(offs[k]), int(offs[k + 1]))
+            E0 = sum(oracle.energy(x[sl], v[sl], m[sl], eps))
+            E1 = sum(oracle.energy(xg[sl], vg[sl], m[sl], eps))
+            dE.append(abs(E1 - E0) / abs(E0))
+        # oracle integration of the worst cluster and up to 7 smaller ones
+        sizes = np.diff(offs)
+        worst = int(np.argmax(dE))
+        cand = [k for k in np.argsort(sizes) if sizes[k] <= 2048 and k != worst]
+        picks = [worst] + [int(k) for k in cand[::max(1, len(cand) // 7)][:7]]
+        orc = []
+        prm = oracle.params(eps, eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3)
+        for k in picks:
+            sl = slice(int(offs[k]), int(offs[k + 1]))
+            if sizes[k] > 4096:
+                continue
+            ref = oracle.System(x[sl], v[sl], m[sl], prm)
+            E0 = sum(ref.energy())
+            ref.run(t_full)
+            E1 = sum(ref.energy())
+            orc.append({"cluster": k, "n": int(sizes[k]), "gpu_dE_over_E": dE[k],
+                        "oracle_dE_over_E": abs(E1 - E0) / abs(E0)})
+            log(f"cluster {k} (N={sizes[k]}): |dE/E| gpu {dE[k]:.2e} oracle {orc[-1]['oracle_dE_over_E']:.2e}")
+        res["oracle_clusters"] = orc
+        res["full"] = {"t_end": t_full, "ensemble_s": t_f, "ensemble_steps": steps,
+                       "interactions": s1["interactions"] - s0["interactions"],
+                       "interactions_per_s": (s1["interactions"] - s0["interactions"]) / t_f,
+                       "all_at_t_end": bool(np.all(tg == t_full)),
+                       "max_abs_dE_over_E": float(max(dE)), "median_abs_dE_over_E":
+                       float(np.median(dE))}
+        log(f"ensemble to t={t_full}: {t_f:.3f} s, max |dE/E| {max(dE):.2e}")
+    g.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +320,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--blocksizes", type=int, default=0,
+                    help="also measure force-only rates per block size at this N (e.g. 1048576)")
+    ap.add_argument("--ensemble", type=int, default=0,
+                    help="also run the ensemble workload with this many clusters (e.g. 256)")
+    ap.add_argument("--ensemble-t", type=float, default=1.0 / 64)
+    ap.add_argument("--ensemble-full", type=float, default=0.0)
+    ap.add_argument("--no-per-cluster", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -208,7 +362,7 @@ def main():
         energy = {"dE_over_E_t0.125": (E1 - E0) / abs(E0), "E0": E0}
         log(f"energy: dE/E = {(E1 - E0) / abs(E0):.3e}")
 
-    sweep_pot_ms = mixed.sweep_with_potential_ms()
+    sweep_nopot_ms = mixed.sweep_without_potential_ms()
     total_ms = sum(mixed.step_ms)
     total_inter = sum(mixed.inter)
     value = total_inter / (total_ms * 1e-3)
@@ -241,6 +395,11 @@ def main():
         cpu, accuracy = cpu_baseline(x, v, m, sw, args.cpu_seconds)
         log(f"cpu oracle: {cpu['value']:.3e} interactions/s on {cpu['cores']} threads")
 
+    extra_bs = blocksize_sweep(torch, args.blocksizes, not args.no_cpu_baseline) \
+        if args.blocksizes else None
+    extra_ens = ensemble_bench(torch, args.ensemble, args.ensemble_t, args.ensemble_full,
+                               not args.no_per_cluster) if args.ensemble else None
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -261,8 +420,12 @@ def main():
                    "block_steps_per_step": mixed.block_steps,
                    "autotuned_shapes": mixed.tuning},
         "full_sweep": {"ms": sweep_ms, "interactions_per_s": sweep_rate,
-                       "ms_with_potential": sweep_pot_ms},
-        "roofline": {"bound": "alu", "kernel": "k_force (mixed, n=N full sweep)",
+                       "returns": "acc, jerk, potential (FP64, 56 B per particle)",
+                       "ms_acc_jerk_only": sweep_nopot_ms,
+                       "interactions_per_s_acc_jerk_only":
+                           float(args.n) * args.n / (sweep_nopot_ms * 1e-3)},
+        "roofline": {"bound": "alu",
+                     "kernel": "k_force<1,1,256,mixed,potential> (the n=N full sweep)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK_FP32, "traffic": None,
                      "flops_per_interaction": FLOPS_PER_INTERACTION},
@@ -270,6 +433,8 @@ def main():
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "energy": energy,
+        "block_sizes": extra_bs,
+        "ensemble": extra_ens,
         "context": {"grape6af_interactions_per_s": 1.0 / 4.3e-10,
                     "grape6af_simultaneous_interactions": 42},
     }

@@ -64,31 +64,62 @@ struct Acc64 {
     double ax, ay, az, jx, jy, jz, p;
 };
 
+// Occupancy target: the mixed one-lane-per-i shape holds 5 waves per SIMD
+// (at most 102 VGPRs); the potential sum would otherwise push it to 4.
+template <int I, int LJ, bool MIXED>
+struct ForceOcc {
+    static constexpr int kMinBlocks = (MIXED && I == 1 && LJ == 1) ? 5 : 1;
+};
+
 template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL>
-__global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
+__global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_force(ForceArgs fa) {
     static_assert(LJ == 1 || LJ == 4 || LJ == 16 || LJ == 64 || LJ == 256, "J_LANES");
     static_assert(LJ == 1 || I == 1, "several i per lane only without lane groups");
     constexpr int NI = kWG / LJ;  // i-slots per workgroup
     constexpr int IB = NI * I;    // i-particles per work item
-    constexpr int JPL = JT / LJ;  // j per lane per tile
-    static_assert(JT % LJ == 0 && JT % kWG == 0, "tile");
+    // DIRECT: with 64 or more lanes per i-particle a j is used by at most four
+    // i-slots, so lanes read j straight from global memory (consecutive lanes,
+    // consecutive j) instead of staging tiles in LDS: no barriers in the j loop
+    // and four j per lane in flight per iteration.
+    constexpr bool DIRECT = LJ >= 64;
+    constexpr int JTX = DIRECT ? (JT > 4 * LJ ? JT : 4 * LJ) : JT;  // j per tile step
+    constexpr int JPL = JTX / LJ;  // j per lane per tile step
+    static_assert(JT % LJ == 0 && JT % kWG == 0 && JTX % kWG == 0, "tile");
     // FP32 partial sums are flushed after kFlushJ j per lane
     constexpr int kFlushJ = 128;
     constexpr int CHJ = JPL < kFlushJ ? JPL : kFlushJ;   // j per lane per chunk
     constexpr int NCH = JPL / CHJ;                       // chunks per tile
     constexpr int FLUSH_TILES = NCH > 1 ? 1 : kFlushJ / JPL;
 
-    __shared__ float4 sP[MIXED ? JT : 1];
-    __shared__ float4 sQ[MIXED ? JT : 1];
-    __shared__ float2 sR[MIXED ? JT : 1];
-    __shared__ double2 sA[MIXED ? 1 : JT];
-    __shared__ double2 sB[MIXED ? 1 : JT];
-    __shared__ double2 sC[MIXED ? 1 : JT];
-    __shared__ double sD[MIXED ? 1 : JT];
+    constexpr int LT = DIRECT ? 1 : JT;  // LDS tile entries
+    __shared__ float4 sP[MIXED ? LT : 1];
+    __shared__ float4 sQ[MIXED ? LT : 1];
+    __shared__ float2 sR[MIXED ? LT : 1];
+    __shared__ double2 sA[MIXED ? 1 : LT];
+    __shared__ double2 sB[MIXED ? 1 : LT];
+    __shared__ double2 sC[MIXED ? 1 : LT];
+    __shared__ double sD[MIXED ? 1 : LT];
     __shared__ double sRed[LJ == 256 ? 4 * 7 : 1];
-    // per-lane list of near pairs found in the current tile (tile-local j)
+    // per-lane list of near pairs found in the current tile step (offset in it)
     constexpr int kNearCap = 8;
-    __shared__ uint8_t sNear[MIXED ? I * kNearCap * kWG : 1];
+    __shared__ uint16_t sNear[MIXED ? I * kNearCap * kWG : 1];
+    // j-particle t of the current tile step: from LDS, or (DIRECT) from global
+    // memory with massless far-away padding past the end of the slice
+    auto jP = [&](int64_t tb, int64_t j1, int t) -> float4 {
+        if (!DIRECT)
+            return sP[t];
+        return tb + t < j1 ? fa.jb.P[tb + t] : make_float4(1e18f, 1e18f, 1e18f, 0.f);
+    };
+    auto jQ = [&](int64_t tb, int64_t j1, int t) -> float4 {
+        if (!DIRECT)
+            return sQ[t];
+        return tb + t < j1 ? fa.jb.Q[tb + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    };
+    auto jR = [&](int64_t tb, int64_t j1, int t) -> float2 {
+        if (!DIRECT)
+            return sR[t];
+        return tb + t < j1 ? fa.jb.R[tb + t] : make_float2(0.f, 0.f);
+    };
 
     const int tid = threadIdx.x;
     int lj, li;
@@ -194,7 +225,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
             d2x[ii] = d2y[ii] = d2z[ii] = 0.0;
 
         int tcount = 0;
-        for (int64_t tb = j0; tb < j1; tb += JT) {
+        for (int64_t tb = j0; tb < j1; tb += JTX) {
             int ncnt[I];
             float sc_eff[I];
 #pragma unroll
@@ -202,6 +233,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
                 ncnt[ii] = 0;
                 sc_eff[ii] = MIXED ? scrit[ii] : 0.f;
             }
+            if (!DIRECT) {
             __syncthreads();
 #pragma unroll
             for (int t = tid; t < JT; t += kWG) {
@@ -231,6 +263,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
                 }
             }
             __syncthreads();
+            }
 
             if (MIXED) {
 #pragma unroll
@@ -247,9 +280,9 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
 #pragma unroll
                         for (int g = 0; g < G; g++) {
                             const int t = lj + (ch * CHJ + u + g) * LJ;
-                            p[g] = sP[t];
-                            q[g] = sQ[t];
-                            r[g] = sR[t];
+                            p[g] = jP(tb, j1, t);
+                            q[g] = jQ(tb, j1, t);
+                            r[g] = jR(tb, j1, t);
                         }
                         bool nr[G][I];
                         bool any = false;
@@ -299,7 +332,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
                                 for (int ii = 0; ii < I; ii++) {
                                     if (nr[g][ii] && ncnt[ii] < kNearCap) {
                                         const int t = lj + (ch * CHJ + u + g) * LJ;
-                                        sNear[(ii * kNearCap + ncnt[ii]) * kWG + tid] = (uint8_t)t;
+                                        sNear[(ii * kNearCap + ncnt[ii]) * kWG + tid] = (uint16_t)t;
                                         if (++ncnt[ii] == kNearCap)
                                             sc_eff[ii] = 0.f;
                                     }
@@ -308,7 +341,7 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
                         }
                     }
                     ++tcount;
-                    if (tcount == FLUSH_TILES || (ch == NCH - 1 && tb + JT >= j1)) {
+                    if (tcount == FLUSH_TILES || (ch == NCH - 1 && tb + JTX >= j1)) {
                         tcount = 0;
 #pragma unroll
                         for (int ii = 0; ii < I; ii++) {
@@ -336,9 +369,9 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
                         const int64_t j = tb + t;
                         if (j == gi[ii] || j >= j1)
                             continue;
-                        const float4 p = sP[t];
-                        const float4 q = sQ[t];
-                        const float2 r = sR[t];
+                        const float4 p = jP(tb, j1, t);
+                        const float4 q = jQ(tb, j1, t);
+                        const float2 r = jR(tb, j1, t);
                         const double ex = ((double)p.x - (double)xh[ii]) + ((double)q.x - (double)xl[ii]);
                         const double ey = ((double)p.y - (double)yh[ii]) + ((double)q.y - (double)yl[ii]);
                         const double ez = ((double)p.z - (double)zh[ii]) + ((double)q.z - (double)zl[ii]);
@@ -363,11 +396,22 @@ __global__ __launch_bounds__(kWG) void k_force(ForceArgs fa) {
                 }
             } else {
 #pragma unroll 2
-                for (int t = lj; t < JT; t += LJ) {
-                    const double2 a = sA[t];
-                    const double2 b = sB[t];
-                    const double2 cv = sC[t];
-                    const double vz = sD[t];
+                for (int t = lj; t < JTX; t += LJ) {
+                    double2 a, b, cv;
+                    double vz;
+                    if (DIRECT) {
+                        const int64_t j = tb + t;
+                        const bool in = j < j1;
+                        a = in ? fa.jb.A[j] : make_double2(1e18, 1e18);
+                        b = in ? fa.jb.B[j] : make_double2(1e18, 0.0);
+                        cv = in ? fa.jb.C[j] : make_double2(0.0, 0.0);
+                        vz = in ? fa.jb.D[j] : 0.0;
+                    } else {
+                        a = sA[t];
+                        b = sB[t];
+                        cv = sC[t];
+                        vz = sD[t];
+                    }
 #pragma unroll
                     for (int ii = 0; ii < I; ii++) {
                         const double dx = a.x - X[ii];
@@ -520,6 +564,13 @@ KernelFn lookup(const Shape &sh, int mixed, int pot, int excl) {
 }  // namespace
 
 bool force_shape_supported(const Shape &sh) { return lookup(sh, 1, 0, 0) != nullptr; }
+
+int force_j_step(const Shape &sh) {
+    // must match JTX of k_force
+    if (sh.j_lanes >= 64)
+        return sh.j_tile > 4 * sh.j_lanes ? sh.j_tile : 4 * sh.j_lanes;
+    return sh.j_tile;
+}
 
 int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self) {
     KernelFn fn = lookup(sh, mixed, want_pot, exclude_self);

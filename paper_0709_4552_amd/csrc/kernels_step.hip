@@ -282,6 +282,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
         }
     const int64_t ib_size = ct.ib[cls];
     const int64_t grid = ct.grid[cls];
+    j_tile = ct.jt[cls];
     // one cluster: choose S by the cost model (every thread tries one S)
     if (C == 1) {
         const int64_t n = pl.n_cur[0];
@@ -415,6 +416,7 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
         }
     const int64_t ib_size = ct.ib[cls];
     const int64_t grid = ct.grid[cls];
+    j_tile = ct.jt[cls];
     const int64_t tiles = (Nc + j_tile - 1) / j_tile;
     const int64_t nib = (n + ib_size - 1) / ib_size;
     int64_t key = INT64_MAX;
@@ -471,9 +473,10 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
 // ---------------------------------------------------------------- reduction
 // Sums the per-slice partial results of every slot whose cluster was split
 // into S > 1 j-slices.  Narrow splits (S <= 8): one thread per slot, slices in
-// order.  Wide splits: one wave per slot, lane l adds slices l, l+64, ...,
-// then a fixed butterfly.  Both orders are fixed, so results are bitwise
-// reproducible.  With one cluster only the n live slots are visited.
+// order.  Medium (S <= 64): one wave per slot, lane l adds slices l, l+64, ...,
+// then a fixed butterfly.  Wide: one workgroup per slot and a fixed tree.
+// Every order is fixed, so results are bitwise reproducible.  With one
+// cluster only the n live slots are visited.
 __global__ __launch_bounds__(kWG) void k_reduce(ForceArgs fa, const int32_t *cid,
                                                 int64_t slot_space, const int32_t *s_max) {
     const int smax = uniform_i32(*s_max);
@@ -508,6 +511,49 @@ __global__ __launch_bounds__(kWG) void k_reduce(ForceArgs fa, const int32_t *cid
             fa.out_jerk[2 * fa.out_stride + s] = acc[5];
             if (fa.out_pot)
                 fa.out_pot[s] = acc[6];
+        }
+        return;
+    }
+    if (smax > 64) {
+        // one workgroup per slot: thread t adds slices t, t+256, ...; then a
+        // fixed tree over the 256 threads
+        __shared__ double red[7][kWG];
+        const int t = threadIdx.x;
+        for (int64_t s = blockIdx.x; s < bound; s += gridDim.x) {
+            const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
+            const int64_t k = fa.slots_at_offsets ? s - uniform_i64(fa.off[c]) : s;
+            const int64_t n = uniform_i32(fa.n_cur[c]);
+            const int S = uniform_i32(fa.S[c]);
+            if (k >= n || S <= 1)
+                continue;
+            const int64_t base = uniform_i64(fa.part_begin[c]) + k;
+#pragma unroll
+            for (int q = 0; q < 7; q++) {
+                double sum = 0.0;
+                for (int js = t; js < S; js += kWG)
+                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+                red[q][t] = sum;
+            }
+            __syncthreads();
+            for (int o = kWG / 2; o > 0; o >>= 1) {
+                if (t < o) {
+#pragma unroll
+                    for (int q = 0; q < 7; q++)
+                        red[q][t] += red[q][t + o];
+                }
+                __syncthreads();
+            }
+            if (t == 0) {
+                fa.out_acc[s] = red[0][0];
+                fa.out_acc[fa.out_stride + s] = red[1][0];
+                fa.out_acc[2 * fa.out_stride + s] = red[2][0];
+                fa.out_jerk[s] = red[3][0];
+                fa.out_jerk[fa.out_stride + s] = red[4][0];
+                fa.out_jerk[2 * fa.out_stride + s] = red[5][0];
+                if (fa.out_pot)
+                    fa.out_pot[s] = red[6][0];
+            }
+            __syncthreads();
         }
         return;
     }

@@ -126,6 +126,7 @@ ClassTable class_table(nbody_ctx *c, int want_pot, int excl) {
         ct.min_n[k] = c->cls_min_n[k];
         ct.ib[k] = ib_of(c->cls_shape[k]);
         ct.grid[k] = grid_of(c, k, want_pot, excl);
+        ct.jt[k] = force_j_step(c->cls_shape[k]);
     }
     return ct;
 }

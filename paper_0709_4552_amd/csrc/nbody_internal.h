@@ -48,6 +48,7 @@ struct ClassTable {
     int32_t min_n[kClasses];
     int32_t ib[kClasses];     // i-particles per work item of the class's shape
     int32_t grid[kClasses];   // persistent workgroups of the class's launch
+    int32_t jt[kClasses];     // j-slice granularity of the class's shape
 };
 
 // Predicted j-particle buffer.
@@ -188,6 +189,7 @@ hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, 
 // ---- force (kernels_force.hip) --------------------------------------------
 bool force_shape_supported(const Shape &sh);
 int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self);
+int force_j_step(const Shape &sh);
 hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self,
                         const ForceArgs &fa, int grid, hipStream_t s);
 

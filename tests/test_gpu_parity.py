@@ -314,3 +314,23 @@ def test_autotune_keeps_results(prec):
         assert relerr(acc.T.cpu().numpy(), ra).max() <= TOL[prec]["a"]
         assert relerr(pot.cpu().numpy(), rp).max() <= TOL[prec]["p"]
     g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_config2_block_steps_to_t1_energy(prec):
+    # Plummer N=16384, eps=1/256, block steps in [2^-20, 2^-3], eta=0.01, to t=1
+    note(f"config 2 prec={prec}")
+    x, v, m = plummer(16384, 1002)
+    eps = 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    steps = g.run_until(1.0)
+    xg, vg, _, _, tg, dtg = g.host_state()
+    assert np.all(tg == 1.0)
+    lv = -np.log2(dtg)
+    assert np.all(lv == np.round(lv)) and lv.min() >= 3 and lv.max() <= 20
+    E0 = sum(oracle.energy(x, v, m, eps))
+    E1 = sum(oracle.energy(xg, vg, m, eps))
+    note(f"  steps={steps} dE/E={(E1 - E0) / abs(E0):.3e} stats={g.stats()}")
+    assert abs(E1 - E0) / abs(E0) <= 1e-5
+    g.close()
