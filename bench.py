@@ -35,6 +35,20 @@ N_DEFAULT = 196608
 EPS = 1.0 / 1024
 T_END = 1.0 / 8
 SEED = 1003
+# HBM traffic of the full-sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by the
+# same counters on an elementwise kernel of known size; valid only for the kernel source it was
+# measured on (checked by hash, else "traffic" is reported as null).
+SWEEP_TRAFFIC = {"force_source_sha256_prefix": "d629d004d94c7f9b", "read_bytes": 153.8e6,
+                 "write_bytes": 55.2e6}
+
+
+def sweep_traffic():
+    import hashlib
+    src = os.path.join(ROOT, "paper_0709_4552_amd", "csrc", "kernels_force.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if h != SWEEP_TRAFFIC["force_source_sha256_prefix"]:
+        return None
+    return SWEEP_TRAFFIC["read_bytes"] + SWEEP_TRAFFIC["write_bytes"]
 
 
 def log(msg):
@@ -327,6 +341,9 @@ def main():
     ap.add_argument("--ensemble-t", type=float, default=1.0 / 64)
     ap.add_argument("--ensemble-full", type=float, default=0.0)
     ap.add_argument("--no-per-cluster", action="store_true")
+    ap.add_argument("--sweep-only", type=int, default=0,
+                    help="only time this many full sweeps, then one 512 MiB elementwise "
+                         "copy of known size (for hardware-counter runs); prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -341,6 +358,35 @@ def main():
 
     x, v, m = plummer(args.n, SEED)
     log(f"workload: Plummer N={args.n} seed={SEED} eps=1/1024 to t={T_END}")
+
+    if args.sweep_only:
+        from paper_0709_4552_amd import NBody
+        g = NBody(x, v, m, EPS, eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3,
+                  precision=NBODY_PREC_MIXED)
+        g.init()
+        g.predict(0.0)
+        il = torch.arange(args.n, dtype=torch.int32, device=g.dev)
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ms = []
+        with torch.cuda.stream(g.stream):
+            for _ in range(args.sweep_only):
+                ev0.record(g.stream)
+                g.force_jerk(il, 0.0, want_pot=True)
+                ev1.record(g.stream)
+                torch.cuda.synchronize()
+                ms.append(ev0.elapsed_time(ev1))
+        # plain elementwise copy of known size: 512 MiB read + 512 MiB written
+        src = torch.ones(64 << 20, dtype=torch.float64, device=g.dev)
+        dst = torch.empty_like(src)
+        torch.add(src, 0.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"metric": METRIC, "mode": "sweep-only", "n": args.n, "sweep_ms": ms,
+                          "copy_bytes_each_way": src.numel() * 8,
+                          "algorithmic_bytes_per_sweep": {"read": args.n * 40 * 2,
+                                                          "write": args.n * 56}}), flush=True)
+        g.close()
+        return
 
     mixed = Run(x, v, m, NBODY_PREC_MIXED, torch)
     for w in range(args.warmup):
@@ -425,9 +471,11 @@ def main():
                        "interactions_per_s_acc_jerk_only":
                            float(args.n) * args.n / (sweep_nopot_ms * 1e-3)},
         "roofline": {"bound": "alu",
+                     "traffic_note": "HBM bytes per sweep launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, "
+                                     "calibrated); algorithmic 26.7e6",
                      "kernel": "k_force<1,1,256,mixed,potential> (the n=N full sweep)",
                      "achieved": achieved / 1e12, "peak": PEAK_FP32 / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK_FP32, "traffic": None,
+                     "frac": achieved / PEAK_FP32, "traffic": sweep_traffic(),
                      "flops_per_interaction": FLOPS_PER_INTERACTION},
         "fp64": fp64,
         "cpu_baseline": cpu,

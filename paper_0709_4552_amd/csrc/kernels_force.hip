@@ -160,8 +160,13 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
         c = uniform_i32(c);
         const int64_t local = item - uniform_i64(fa.item_begin[c]);
         const int S = uniform_i32(fa.S[c]);
-        const int64_t ib = local / S;
-        const int js = (int)(local - ib * S);
+        // slice-major order: consecutive items share a j-slice, so workgroups on
+        // all eight XCDs work on the same slice at once and each XCD's L2 fetches
+        // it about once instead of once per i-block
+        const int64_t n_c_items = uniform_i32(fa.n_cur[c]);
+        const int64_t nib_c = (n_c_items + IB - 1) / IB;
+        const int js = (int)(local / nib_c);
+        const int64_t ib = local - (int64_t)js * nib_c;
         const int64_t n_c = uniform_i32(fa.n_cur[c]);
         const int64_t cb = uniform_i64(fa.off[c]), ce = uniform_i64(fa.off[c + 1]);
         const int64_t jl = uniform_i32(fa.jlen[c]);
