@@ -136,12 +136,13 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
     if (uniform_i32(*fa.cls) != fa.my_cls)
         return;
     const int64_t total = uniform_i64(*fa.total_items);
+    // first round static (item = workgroup index); only when there are more
+    // items than workgroups do finished workgroups pop further items from the
+    // queue (items gridDim.x, gridDim.x+1, ...).  Small launches thus take no
+    // atomics at all: same-address atomics from every workgroup serialise in L2
+    // and cost tens of microseconds.
+    int64_t item = blockIdx.x;
     for (;;) {
-        if (tid == fa.fetch_lane)
-            s_item = (int64_t)atomicAdd(fa.item_counter, 1ull);
-        __syncthreads();
-        const int64_t item = uniform_i64(s_item);
-        __syncthreads();
         if (item >= total)
             break;
         // locate the cluster of this item (largest c with item_begin[c] <= item)
@@ -533,6 +534,13 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                 }
             }
         }
+        if (total <= (int64_t)gridDim.x)
+            break;
+        if (tid == fa.fetch_lane)
+            s_item = (int64_t)gridDim.x + (int64_t)atomicAdd(fa.item_counter, 1ull);
+        __syncthreads();
+        item = uniform_i64(s_item);
+        __syncthreads();
     }
 }
 
