@@ -195,10 +195,11 @@ __global__ __launch_bounds__(kWG) void k_select_compact(State st, Params pr, con
 // Builds the work list of one force evaluation: cluster c gets
 // ceil(n_c / ib) i-blocks times S_c j-slices.  The shape class (and so ib)
 // follows the mean block size of the active clusters.  One cluster: S is the
-// value in [1, 64] that minimises the modelled time ceil(items/grid) *
-// (tiles per slice + 1).  Several clusters: S_c follows the cluster's share
-// of the work so the whole evaluation has about 4*grid items; the force
-// kernel's work queue balances the rest.  One workgroup.
+// value in [1, kMaxSlices] that minimises the modelled time
+// ceil(items / plan_grid) * (tiles per slice + 1).  Several clusters: S_c
+// follows the cluster's share of the work so the whole evaluation has about
+// 4*grid items; the force kernel's work queue balances the rest.  One
+// workgroup.
 __device__ int64_t block_exclusive_scan(int64_t v, int64_t *tmp, int64_t *total) {
     const int t = threadIdx.x;
     tmp[t] = v;
@@ -281,7 +282,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
             break;
         }
     const int64_t ib_size = ct.ib[cls];
-    const int64_t grid = ct.grid[cls];
+    const int64_t grid_res = ct.grid[cls];
     j_tile = ct.jt[cls];
     // one cluster: choose S by the cost model (every thread tries one S)
     if (C == 1) {
@@ -289,6 +290,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
         const int64_t Nc = off[1] - off[0];
         const int64_t tiles = (Nc + j_tile - 1) / j_tile;
         const int64_t nib = (n + ib_size - 1) / ib_size;
+        const int64_t grid = plan_grid(grid_res, nib, tiles);
         const int64_t S = t + 1;
         int64_t key = INT64_MAX;
         if (n > 0 && S <= tiles && S <= kMaxSlices && (S == 1 || S * n <= part_cap)) {
@@ -335,7 +337,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
                             s = uniform_i32(s_best_S);
                         } else if (W > 0.0) {
                             const double share = (double)n * (double)Nc / W;
-                            s = (int64_t)ceil(4.0 * (double)grid * share / (double)nib);
+                            s = (int64_t)ceil(4.0 * (double)grid_res * share / (double)nib);
                         }
                         s = s < 1 ? 1 : (s > tiles ? tiles : s);
                     }
@@ -415,10 +417,11 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
             break;
         }
     const int64_t ib_size = ct.ib[cls];
-    const int64_t grid = ct.grid[cls];
+    const int64_t grid_res = ct.grid[cls];
     j_tile = ct.jt[cls];
     const int64_t tiles = (Nc + j_tile - 1) / j_tile;
     const int64_t nib = (n + ib_size - 1) / ib_size;
+    const int64_t grid = plan_grid(grid_res, nib, tiles);
     int64_t key = INT64_MAX;
     for (int64_t S = lane + 1; S <= kMaxSlices && S <= tiles; S += 64) {
         if (n <= 0 || (S > 1 && S * n > part_cap))

@@ -40,6 +40,16 @@ struct DevCtl {
 };
 
 constexpr int kMaxSlices = 1024;   // j-slices per cluster the planner may choose
+// Workgroups of one launch do not run at equal speed, so when each takes a
+// single long item the slowest sets the launch time.  The planner therefore
+// sizes items against a virtual grid of 4x (2x) the resident one, so that the
+// queue hands every workgroup several, once each workgroup has at least 16 (4)
+// tile-units of work (i-blocks x j-tiles / grid); below that, slices of only a
+// tile or two would cost more in per-item overhead than they save.
+__host__ __device__ inline int64_t plan_grid(int64_t grid, int64_t nib, int64_t tiles) {
+    const int64_t u = nib * tiles;
+    return u >= 16 * grid ? 4 * grid : (u >= 4 * grid ? 2 * grid : grid);
+}
 
 // Launch-shape classes by block size: class k is used when the mean block
 // size of the active clusters is >= min_n[k] (classes in decreasing order).
