@@ -203,9 +203,17 @@ int nbody_correct(nbody_ctx *ctx, const int32_t *i_list_dev, int64_t n, double t
 
 /*
  * One block step of every cluster, driven entirely from the device: select,
- * predict, force, correct.  Nothing is read back unless t_out or n_out is
- * non-NULL; then the call synchronises and returns the new time of cluster 0
- * and the block size summed over clusters.
+ * predict, force, correct.  The call first checks that the state is a
+ * synchronised block-step state (below) and synchronises to do so; it returns
+ * the new time of cluster 0 and the block size summed over clusters in
+ * t_out / n_out when these are non-NULL.
+ *
+ * Synchronised block-step state (section 4.1): within each cluster every
+ * particle's last time t_i precedes every particle's next time t_i + dt_i,
+ * and t_i is a multiple of dt_i.  nbody_init and block steps keep it;
+ * explicit corrections keep it when they correct whole blocks.  Otherwise
+ * (for example after correcting only part of a due block) nbody_step_block
+ * and nbody_run_until return ESTATE and step nothing.
  */
 int nbody_step_block(nbody_ctx *ctx, double *t_out, int64_t *n_out);
 
@@ -214,8 +222,9 @@ int nbody_step_block(nbody_ctx *ctx, double *t_out, int64_t *n_out);
  * step 6).  Steps are replayed from a captured HIP graph in batches; with
  * steps of 2^dt_max_log2 or less and t_end a multiple of 2^dt_max_log2,
  * every particle ends exactly at t_end.  t_end must be a multiple of
- * 2^dt_min_log2.  Synchronises; *n_steps_out (may be NULL) receives the
- * number of ensemble block steps that did work.
+ * 2^dt_min_log2.  The state must be a synchronised block-step state (see
+ * nbody_step_block), else ESTATE.  Synchronises; *n_steps_out (may be NULL)
+ * receives the number of ensemble block steps that did work.
  */
 int nbody_run_until(nbody_ctx *ctx, double t_end, int64_t *n_steps_out);
 

@@ -133,7 +133,8 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
     }
 
     __shared__ int64_t s_item;
-    if (uniform_i32(*fa.cls) != fa.my_cls)
+    // the plan picks one class; a launch serves every class sharing its shape
+    if (((fa.cls_mask >> uniform_i32(*fa.cls)) & 1) == 0)
         return;
     const int64_t total = uniform_i64(*fa.total_items);
     // first round static (item = workgroup index); only when there are more

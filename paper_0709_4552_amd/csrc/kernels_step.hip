@@ -3,6 +3,7 @@
 // j-particle buffer written by the predictor.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <climits>
 
 #include "nbody_internal.h"
@@ -46,8 +47,46 @@ __global__ void k_iota_i32(int32_t *p, int64_t n) {
 }
 
 // ---------------------------------------------------------------- predictor
-// Third-order Taylor prediction of every particle to its cluster's time
-// (section 4.1, step 3), written to the j-particle buffer.
+// Third-order Taylor prediction of particle i to time T (section 4.1, step 3),
+// written to the j-particle buffer.
+template <int MIXED>
+__device__ inline void predict_one(const State &st, const Params &pr, const JBuf &jb, int64_t i,
+                                   int64_t tick_i, int64_t T) {
+    const double d = (double)(T - tick_i) * pr.tick;
+    const double h = 0.5 * d, s6 = d * (1.0 / 6.0);
+    const double ax = st.ax[i], ay = st.ay[i], az = st.az[i];
+    const double jx = st.jx[i], jy = st.jy[i], jz = st.jz[i];
+    const double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
+    // xp = x + d (v + d (a/2 + d j/6)),  vp = v + d (a + d j/2)
+    const double xp = fma(d, fma(d, fma(s6, jx, 0.5 * ax), vx), st.x[i]);
+    const double yp = fma(d, fma(d, fma(s6, jy, 0.5 * ay), vy), st.y[i]);
+    const double zp = fma(d, fma(d, fma(s6, jz, 0.5 * az), vz), st.z[i]);
+    const double vxp = fma(d, fma(h, jx, ax), vx);
+    const double vyp = fma(d, fma(h, jy, ay), vy);
+    const double vzp = fma(d, fma(h, jz, az), vz);
+    const double m = st.m[i];
+    if (MIXED) {
+        // hi on a fixed grid: differences of hi parts are exact, so the
+        // rounding of x_j - x_i does not depend on i's low bits
+        const float xh = (float)(rint(xp * pr.grid_inv) * pr.grid_q);
+        const float yh = (float)(rint(yp * pr.grid_inv) * pr.grid_q);
+        const float zh = (float)(rint(zp * pr.grid_inv) * pr.grid_q);
+        const float xl = (float)(xp - (double)xh);
+        const float yl = (float)(yp - (double)yh);
+        const float zl = (float)(zp - (double)zh);
+        jb.P[i] = make_float4(xh, yh, zh, (float)m);
+        jb.Q[i] = make_float4(xl, yl, zl, (float)vxp);
+        jb.R[i] = make_float2((float)vyp, (float)vzp);
+    } else {
+        jb.A[i] = make_double2(xp, yp);
+        jb.B[i] = make_double2(zp, m);
+        jb.C[i] = make_double2(vxp, vyp);
+        jb.D[i] = vzp;
+    }
+}
+
+// Prediction of every particle, to the host's time or to its cluster's
+// planned time (clusters with an empty block are skipped).
 template <int MIXED>
 __global__ __launch_bounds__(kWG) void k_predict(State st, Params pr, JBuf jb, const int32_t *cid,
                                                   const int64_t *t_cur, const int32_t *n_cur,
@@ -61,37 +100,7 @@ __global__ __launch_bounds__(kWG) void k_predict(State st, Params pr, JBuf jb, c
                 continue;
             T = t_cur[c];
         }
-        const double d = (double)(T - st.tick[i]) * pr.tick;
-        const double h = 0.5 * d, s6 = d * (1.0 / 6.0);
-        const double ax = st.ax[i], ay = st.ay[i], az = st.az[i];
-        const double jx = st.jx[i], jy = st.jy[i], jz = st.jz[i];
-        const double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
-        // xp = x + d (v + d (a/2 + d j/6)),  vp = v + d (a + d j/2)
-        const double xp = fma(d, fma(d, fma(s6, jx, 0.5 * ax), vx), st.x[i]);
-        const double yp = fma(d, fma(d, fma(s6, jy, 0.5 * ay), vy), st.y[i]);
-        const double zp = fma(d, fma(d, fma(s6, jz, 0.5 * az), vz), st.z[i]);
-        const double vxp = fma(d, fma(h, jx, ax), vx);
-        const double vyp = fma(d, fma(h, jy, ay), vy);
-        const double vzp = fma(d, fma(h, jz, az), vz);
-        const double m = st.m[i];
-        if (MIXED) {
-            // hi on a fixed grid: differences of hi parts are exact, so the
-            // rounding of x_j - x_i does not depend on i's low bits
-            const float xh = (float)(rint(xp * pr.grid_inv) * pr.grid_q);
-            const float yh = (float)(rint(yp * pr.grid_inv) * pr.grid_q);
-            const float zh = (float)(rint(zp * pr.grid_inv) * pr.grid_q);
-            const float xl = (float)(xp - (double)xh);
-            const float yl = (float)(yp - (double)yh);
-            const float zl = (float)(zp - (double)zh);
-            jb.P[i] = make_float4(xh, yh, zh, (float)m);
-            jb.Q[i] = make_float4(xl, yl, zl, (float)vxp);
-            jb.R[i] = make_float2((float)vyp, (float)vzp);
-        } else {
-            jb.A[i] = make_double2(xp, yp);
-            jb.B[i] = make_double2(zp, m);
-            jb.C[i] = make_double2(vxp, vyp);
-            jb.D[i] = vzp;
-        }
+        predict_one<MIXED>(st, pr, jb, i, st.tick[i], T);
     }
 }
 
@@ -121,74 +130,132 @@ __global__ void k_read_predicted(Params pr, JBuf jb, double *pos, double *vel, i
 }
 
 // ---------------------------------------------------------------- selection
-// Section 4.1, step 2: next time of each cluster = min_i (t_i + dt_i), then
-// the block of particles due at that time.  One workgroup per chunk of at
-// most kChunk particles of one cluster.
-__global__ __launch_bounds__(kWG) void k_select_min(State st, Params pr, const int64_t *off,
-                                                    const int32_t *chunk_c,
-                                                    const int64_t *chunk_b, int64_t *t_next) {
-    __shared__ unsigned long long red[kWG / 64];
+// Block-step scheme (section 4.1, steps 1-2).  A particle on level L (step
+// dt_L = 2^-L) is stepped only at multiples of dt_L, and every particle was
+// last stepped at or before its cluster's latest block time t_now.  So its
+// last time is the latest multiple of dt_L not after t_now, and its next time
+// the following multiple: all particles of one level share it.  The next block
+// time is therefore the minimum of that over the occupied levels, and the block
+// is every particle on a level whose step divides it.  The per-level counts of
+// each cluster, kept up to date by the corrector, give both without a scan.
+__device__ inline int64_t level_next(int64_t t_now, int shift) {
+    return ((t_now >> shift) + 1) << shift;  // arithmetic shift: floor, also for t_now = -1
+}
+
+// Priming scan before a run of block steps: level counts, earliest next time
+// and latest last time of each cluster.  A valid block-step state has every
+// last time before every next time and each last time a multiple of the
+// particle's step; anything else is flagged as not due.
+__global__ __launch_bounds__(kWG) void k_prime(State st, Params pr, const int64_t *off,
+                                               const int32_t *chunk_c, const int64_t *chunk_b,
+                                               int32_t *lev_cnt, int64_t *t_min, int64_t *t_max,
+                                               DevCtl *ctl) {
+    __shared__ int32_t hist[kLevels];
+    __shared__ unsigned long long rmin[kWG / 64], rmax[kWG / 64];
+    if (threadIdx.x < kLevels)
+        hist[threadIdx.x] = 0;
+    __syncthreads();
     const int64_t k = blockIdx.x;
     const int c = uniform_i32(chunk_c[k]);
     const int64_t b = uniform_i64(chunk_b[k]);
     const int64_t e = min(uniform_i64(off[c + 1]), b + kChunk);
-    unsigned long long best = ULLONG_MAX;
-    for (int64_t i = b + threadIdx.x; i < e; i += kWG) {
-        const unsigned long long nt = (unsigned long long)(st.tick[i] + dt_ticks(pr.lev_max, st.lev[i]));
-        best = nt < best ? nt : best;
+    const int64_t i = b + threadIdx.x;
+    unsigned long long nmin = ULLONG_MAX, tmax = 0;
+    int32_t err = 0;
+    if (i < e) {
+        const int lev = st.lev[i];
+        const int64_t tk = st.tick[i];
+        if (lev < pr.lev_min || lev > pr.lev_max || tk < 0) {
+            err = kErrNotDue;
+        } else {
+            const int64_t dtk = dt_ticks(pr.lev_max, lev);
+            if (tk & (dtk - 1))
+                err = kErrNotDue;
+            atomicAdd(&hist[lev], 1);
+            nmin = (unsigned long long)(tk + dtk);
+            tmax = (unsigned long long)tk;
+        }
     }
     for (int o = 32; o > 0; o >>= 1) {
-        const unsigned long long v = __shfl_xor(best, o);
-        best = v < best ? v : best;
+        const unsigned long long a = __shfl_xor(nmin, o), m = __shfl_xor(tmax, o);
+        nmin = a < nmin ? a : nmin;
+        tmax = m > tmax ? m : tmax;
     }
-    if ((threadIdx.x & 63) == 0)
-        red[threadIdx.x >> 6] = best;
+    if ((threadIdx.x & 63) == 0) {
+        rmin[threadIdx.x >> 6] = nmin;
+        rmax[threadIdx.x >> 6] = tmax;
+    }
+    if (err)
+        atomicOr(&ctl->err, err);
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < kWG / 64; w++)
-            best = red[w] < best ? red[w] : best;
-        atomicMin((unsigned long long *)&t_next[c], best);
+        for (int w = 1; w < kWG / 64; w++) {
+            nmin = rmin[w] < nmin ? rmin[w] : nmin;
+            tmax = rmax[w] > tmax ? rmax[w] : tmax;
+        }
+        atomicMin((unsigned long long *)&t_min[c], nmin);
+        atomicMax((unsigned long long *)&t_max[c], tmax);
+    }
+    if (threadIdx.x < kLevels && hist[threadIdx.x] != 0)
+        atomicAdd(&lev_cnt[(int64_t)c * kLevels + threadIdx.x], hist[threadIdx.x]);
+}
+
+// t_now = (earliest next time) - 1: every level's next time computed from it is
+// then the true one, provided the state passed the checks above.
+__global__ void k_prime_finish(Params pr, const int64_t *t_min, const int64_t *t_max,
+                               int64_t *t_now, DevCtl *ctl) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < pr.C; c += gridDim.x * blockDim.x) {
+        if (t_max[c] >= t_min[c])
+            atomicOr(&ctl->err, kErrNotDue);
+        t_now[c] = t_min[c] - 1;
     }
 }
 
-__global__ __launch_bounds__(kWG) void k_select_compact(State st, Params pr, const int64_t *off,
-                                                        const int32_t *chunk_c,
-                                                        const int64_t *chunk_b,
-                                                        const int64_t *t_next, int32_t *n_act,
-                                                        int32_t *i_list, const DevCtl *ctl) {
+// One block step's scan (after the plan): predict every particle of a stepping
+// cluster to the block time and append the particles due then to the active
+// list.  One workgroup per chunk, one particle per thread.
+template <int MIXED>
+__global__ __launch_bounds__(kWG) void k_predict_compact(State st, Params pr, JBuf jb,
+                                                         const int64_t *off,
+                                                         const int32_t *chunk_c,
+                                                         const int64_t *chunk_b, PlanDev pl,
+                                                         int32_t *cursor, int32_t *i_list) {
+    static_assert(kChunk == kWG, "one particle per thread");
     __shared__ int32_t wcount[kWG / 64];
     __shared__ int32_t base_s;
     const int64_t k = blockIdx.x;
     const int c = uniform_i32(chunk_c[k]);
-    const int64_t T = uniform_i64(t_next[c]);
-    if (T > uniform_i64(ctl->t_end_tick))
+    if (uniform_i32(pl.n_cur[c]) == 0)
         return;
+    const int64_t T = uniform_i64(pl.t_cur[c]);
     const int64_t cb = uniform_i64(off[c]);
     const int64_t b = uniform_i64(chunk_b[k]);
     const int64_t e = min(uniform_i64(off[c + 1]), b + kChunk);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    for (int64_t base = b; base < e; base += kWG) {
-        const int64_t i = base + threadIdx.x;
-        const bool due = i < e && st.tick[i] + dt_ticks(pr.lev_max, st.lev[i]) == T;
-        const unsigned long long bal = __ballot(due);
-        const int before = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0)
-            wcount[w] = __popcll(bal);
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            int tot = 0;
-            for (int q = 0; q < kWG / 64; q++) {
-                const int cnt = wcount[q];
-                wcount[q] = tot;
-                tot += cnt;
-            }
-            base_s = tot ? atomicAdd(&n_act[c], tot) : 0;
-        }
-        __syncthreads();
-        if (due)
-            i_list[cb + base_s + wcount[w] + before] = (int32_t)i;
-        __syncthreads();
+    const int64_t i = b + threadIdx.x;
+    bool due = false;
+    if (i < e) {
+        const int64_t tk = st.tick[i];
+        due = tk + dt_ticks(pr.lev_max, st.lev[i]) == T;
+        predict_one<MIXED>(st, pr, jb, i, tk, T);
     }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(due);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0)
+        wcount[w] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < kWG / 64; q++) {
+            const int cnt = wcount[q];
+            wcount[q] = tot;
+            tot += cnt;
+        }
+        base_s = tot ? atomicAdd(&cursor[c], tot) : 0;
+    }
+    __syncthreads();
+    if (due)
+        i_list[cb + base_s + wcount[w] + before] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------- planning
@@ -200,6 +267,27 @@ __global__ __launch_bounds__(kWG) void k_select_compact(State st, Params pr, con
 // follows the cluster's share of the work so the whole evaluation has about
 // 4*grid items; the force kernel's work queue balances the rest.  One
 // workgroup.
+// Next block of cluster c from its level counts (one thread).  n = 0 when the
+// cluster's next time lies beyond t_end; then the cluster's time stays.
+__device__ inline int32_t block_from_levels(const Params &pr, const PlanDev &pl, int c,
+                                            int64_t t_end, int64_t *T_out) {
+    const int32_t *cnt = pl.lev_cnt + (int64_t)c * kLevels;
+    const int64_t tnow = pl.t_now[c];
+    int64_t T = INT64_MAX;
+    for (int L = pr.lev_min; L <= pr.lev_max; L++)
+        if (cnt[L] > 0) {
+            const int64_t t = level_next(tnow, pr.lev_max - L);
+            T = t < T ? t : T;
+        }
+    int32_t n = 0;
+    if (T != INT64_MAX && T <= t_end)
+        for (int L = pr.lev_min; L <= pr.lev_max; L++)
+            if (cnt[L] > 0 && (T & (dt_ticks(pr.lev_max, L) - 1)) == 0)
+                n += cnt[L];
+    *T_out = n > 0 ? T : tnow;
+    return n;
+}
+
 __device__ int64_t block_exclusive_scan(int64_t v, int64_t *tmp, int64_t *total) {
     const int t = threadIdx.x;
     tmp[t] = v;
@@ -229,6 +317,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
     __shared__ int s_best_S;
     const int t = threadIdx.x;
     const int C = pr.C;
+    const int64_t t_end = ctl->t_end_tick;
     if (t == 0)
         ctl->s_max = 0;
     // pass 1: take the block sizes of this step; total work
@@ -239,11 +328,17 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
         if (host_n >= 0) {
             n = host_n;
             pl.t_cur[c] = host_t;
-        } else {
+        } else if (host_n == kPlanFromLists) {
             n = n_act[c];
             pl.t_cur[c] = t_next[c];
             n_act[c] = 0;
             t_next[c] = LLONG_MAX;
+        } else {
+            int64_t T;
+            n = block_from_levels(pr, pl, c, t_end, &T);
+            pl.t_cur[c] = T;
+            pl.t_now[c] = T;
+            n_act[c] = 0;  // compaction cursor
         }
         pl.n_cur[c] = n;
         const double nc = (double)(off[c + 1] - off[c]);
@@ -399,15 +494,36 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
                                                  int64_t part_cap, ClassTable ct, int32_t j_tile,
                                                  int32_t host_n, int64_t host_t,
                                                  int32_t count_stats) {
+    static_assert(kLevels == 64, "one level per lane");
     const int lane = threadIdx.x;
     int64_t n;
     int64_t tcur;
     if (host_n >= 0) {
         n = host_n;
         tcur = host_t;
-    } else {
+    } else if (host_n == kPlanFromLists) {
         n = uniform_i32(n_act[0]);
         tcur = uniform_i64(t_next[0]);
+    } else {
+        // lane L looks at level L
+        const bool in = lane >= pr.lev_min && lane <= pr.lev_max;
+        const int32_t cnt = in ? pl.lev_cnt[lane] : 0;
+        const int sh = in ? pr.lev_max - lane : 0;
+        const int64_t tnow = uniform_i64(pl.t_now[0]);
+        int64_t T = cnt > 0 ? level_next(tnow, sh) : INT64_MAX;
+        for (int o = 32; o > 0; o >>= 1) {
+            const int64_t other = __shfl_xor(T, o);
+            T = other < T ? other : T;
+        }
+        int32_t due = (cnt > 0 && T != INT64_MAX && (T & (((int64_t)1 << sh) - 1)) == 0) ? cnt : 0;
+        for (int o = 32; o > 0; o >>= 1)
+            due += __shfl_xor(due, o);
+        n = uniform_i32(due);
+        tcur = uniform_i64(T);
+        if (tcur == INT64_MAX || tcur > uniform_i64(ctl->t_end_tick)) {
+            n = 0;
+            tcur = tnow;
+        }
     }
     const int64_t Nc = off[1] - off[0];
     int cls = kClasses - 1;
@@ -448,9 +564,12 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
         items = nib * Sfin;
         parts = Sfin > 1 ? (int64_t)Sfin * n : 0;
     }
-    if (host_n < 0) {
+    if (host_n == kPlanFromLists) {
         n_act[0] = 0;
         t_next[0] = LLONG_MAX;
+    } else if (host_n == kPlanFromLevels) {
+        n_act[0] = 0;  // compaction cursor
+        pl.t_now[0] = tcur;
     }
     pl.n_cur[0] = (int32_t)n;
     pl.t_cur[0] = tcur;
@@ -473,130 +592,77 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
     }
 }
 
-// ---------------------------------------------------------------- reduction
-// Sums the per-slice partial results of every slot whose cluster was split
-// into S > 1 j-slices.  Narrow splits (S <= 8): one thread per slot, slices in
-// order.  Medium (S <= 64): one wave per slot, lane l adds slices l, l+64, ...,
-// then a fixed butterfly.  Wide: one workgroup per slot and a fixed tree.
-// Every order is fixed, so results are bitwise reproducible.  With one
-// cluster only the n live slots are visited.
-__global__ __launch_bounds__(kWG) void k_reduce(ForceArgs fa, const int32_t *cid,
-                                                int64_t slot_space, const int32_t *s_max) {
-    const int smax = uniform_i32(*s_max);
-    if (smax <= 1)
-        return;
-    int64_t bound = slot_space;
-    if (fa.C == 1)
-        bound = min(bound, (int64_t)uniform_i32(fa.n_cur[0]));
-    if (smax <= 8) {
-        for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < bound;
-             s += (int64_t)gridDim.x * blockDim.x) {
-            const int c = fa.C > 1 ? cid[s] : 0;
-            const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
-            const int64_t n = fa.n_cur[c];
-            const int S = fa.S[c];
-            if (k >= n || S <= 1)
-                continue;
-            const int64_t base = fa.part_begin[c] + k;
-            double acc[7];
-#pragma unroll
-            for (int q = 0; q < 7; q++) {
-                double sum = 0.0;
-                for (int js = 0; js < S; js++)
-                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
-                acc[q] = sum;
-            }
-            fa.out_acc[s] = acc[0];
-            fa.out_acc[fa.out_stride + s] = acc[1];
-            fa.out_acc[2 * fa.out_stride + s] = acc[2];
-            fa.out_jerk[s] = acc[3];
-            fa.out_jerk[fa.out_stride + s] = acc[4];
-            fa.out_jerk[2 * fa.out_stride + s] = acc[5];
-            if (fa.out_pot)
-                fa.out_pot[s] = acc[6];
-        }
-        return;
+// ---------------------------------------------------------------- corrector
+// Section 4.1, step 5: Hermite correction of particle i at time T from its new
+// acceleration and jerk, and its next step level (Aarseth criterion, then the
+// power-of-two quantisation).  Returns the new level, or -1 when the particle
+// was not due at T (then nothing is written).
+__device__ inline int correct_particle(const State &st, const Params &pr, int64_t i, int64_t T,
+                                       const double a1[3], const double j1[3], int32_t &err,
+                                       unsigned long long &clamps) {
+    const int lev = st.lev[i];
+    const int64_t dtk = dt_ticks(pr.lev_max, lev);
+    if (st.tick[i] + dtk != T) {
+        err |= kErrNotDue;
+        return -1;
     }
-    if (smax > 64) {
-        // one workgroup per slot: thread t adds slices t, t+256, ...; then a
-        // fixed tree over the 256 threads
-        __shared__ double red[7][kWG];
-        const int t = threadIdx.x;
-        for (int64_t s = blockIdx.x; s < bound; s += gridDim.x) {
-            const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
-            const int64_t k = fa.slots_at_offsets ? s - uniform_i64(fa.off[c]) : s;
-            const int64_t n = uniform_i32(fa.n_cur[c]);
-            const int S = uniform_i32(fa.S[c]);
-            if (k >= n || S <= 1)
-                continue;
-            const int64_t base = uniform_i64(fa.part_begin[c]) + k;
+    const double dt = ldexp(1.0, -lev);
+    const double h = 0.5 * dt, s6 = dt * (1.0 / 6.0);
+    const double x0[3] = {st.x[i], st.y[i], st.z[i]};
+    const double v0[3] = {st.vx[i], st.vy[i], st.vz[i]};
+    const double a0[3] = {st.ax[i], st.ay[i], st.az[i]};
+    const double j0[3] = {st.jx[i], st.jy[i], st.jz[i]};
+    double x1[3], v1[3], a2e[3], a3[3];
+    const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
+    const double idt2 = 1.0 / dt2, idt3 = 1.0 / dt3;  // exact: powers of two
 #pragma unroll
-            for (int q = 0; q < 7; q++) {
-                double sum = 0.0;
-                for (int js = t; js < S; js += kWG)
-                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
-                red[q][t] = sum;
-            }
-            __syncthreads();
-            for (int o = kWG / 2; o > 0; o >>= 1) {
-                if (t < o) {
-#pragma unroll
-                    for (int q = 0; q < 7; q++)
-                        red[q][t] += red[q][t + o];
-                }
-                __syncthreads();
-            }
-            if (t == 0) {
-                fa.out_acc[s] = red[0][0];
-                fa.out_acc[fa.out_stride + s] = red[1][0];
-                fa.out_acc[2 * fa.out_stride + s] = red[2][0];
-                fa.out_jerk[s] = red[3][0];
-                fa.out_jerk[fa.out_stride + s] = red[4][0];
-                fa.out_jerk[2 * fa.out_stride + s] = red[5][0];
-                if (fa.out_pot)
-                    fa.out_pot[s] = red[6][0];
-            }
-            __syncthreads();
-        }
-        return;
+    for (int q = 0; q < 3; q++) {
+        const double xp = fma(dt, fma(dt, fma(s6, j0[q], 0.5 * a0[q]), v0[q]), x0[q]);
+        const double vp = fma(dt, fma(h, j0[q], a0[q]), v0[q]);
+        const double da = a0[q] - a1[q];
+        const double a2 = (-6.0 * da - dt * (4.0 * j0[q] + 2.0 * j1[q])) * idt2;
+        const double a3q = (12.0 * da + 6.0 * dt * (j0[q] + j1[q])) * idt3;
+        x1[q] = xp + a2 * dt4 / 24.0 + a3q * dt5 / 120.0;
+        v1[q] = vp + a2 * dt3 / 6.0 + a3q * dt4 / 24.0;
+        a2e[q] = a2 + dt * a3q;
+        a3[q] = a3q;
     }
-    const int lane = threadIdx.x & 63;
-    const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t s = wave; s < bound; s += nwaves) {
-        const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
-        const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
-        const int64_t n = fa.n_cur[c];
-        const int S = fa.S[c];
-        if (k >= n || S <= 1)
-            continue;
-        const int64_t base = fa.part_begin[c] + k;
-        double acc[7];
-#pragma unroll
-        for (int q = 0; q < 7; q++) {
-            double sum = 0.0;
-            for (int js = lane; js < S; js += 64)
-                sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1)
-                sum += __shfl_xor(sum, o);
-            acc[q] = sum;
-        }
-        if (lane == 0) {
-            fa.out_acc[s] = acc[0];
-            fa.out_acc[fa.out_stride + s] = acc[1];
-            fa.out_acc[2 * fa.out_stride + s] = acc[2];
-            fa.out_jerk[s] = acc[3];
-            fa.out_jerk[fa.out_stride + s] = acc[4];
-            fa.out_jerk[2 * fa.out_stride + s] = acc[5];
-            if (fa.out_pot)
-                fa.out_pot[s] = acc[6];
-        }
+    if (!(finite3(x1[0], x1[1], x1[2]) && finite3(v1[0], v1[1], v1[2]) &&
+          finite3(a1[0], a1[1], a1[2]) && finite3(j1[0], j1[1], j1[2])))
+        err |= kErrNonFinite;
+    // Aarseth criterion and block quantisation
+    const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
+    const double na2 = norm3(a2e[0], a2e[1], a2e[2]), na3 = norm3(a3[0], a3[1], a3[2]);
+    const double num = na * na2 + nj * nj;
+    const double den = nj * na3 + na2 * na2;
+    const double dt_raw = den > 0.0 ? sqrt(pr.eta * num / den) : INFINITY;
+    int nlev = lev;
+    if (dt_raw < dt) {
+        while (nlev < pr.lev_max && ldexp(1.0, -nlev) > dt_raw)
+            nlev++;
+        if (ldexp(1.0, -nlev) > dt_raw)
+            clamps++;
+    } else if (dt_raw >= 2.0 * dt && lev > pr.lev_min && (T % (2 * dtk)) == 0) {
+        nlev = lev - 1;
     }
+    st.x[i] = x1[0];
+    st.y[i] = x1[1];
+    st.z[i] = x1[2];
+    st.vx[i] = v1[0];
+    st.vy[i] = v1[1];
+    st.vz[i] = v1[2];
+    st.ax[i] = a1[0];
+    st.ay[i] = a1[1];
+    st.az[i] = a1[2];
+    st.jx[i] = j1[0];
+    st.jy[i] = j1[1];
+    st.jz[i] = j1[2];
+    st.tick[i] = T;
+    st.lev[i] = (int8_t)nlev;
+    return nlev;
 }
 
-// ---------------------------------------------------------------- corrector
-// Section 4.1, step 5: Hermite correction of the block and its new steps.
+// Correction of a caller-given list (the explicit entry point).
 __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int32_t *i_list,
                                                  int32_t slots_at_offsets, const int64_t *off,
                                                  const int32_t *cid, const int32_t *n_cur,
@@ -618,75 +684,214 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
             err |= kErrRange;
             continue;
         }
-        const int64_t T = t_cur[c];
-        const int lev = st.lev[i];
-        const int64_t dtk = dt_ticks(pr.lev_max, lev);
-        if (st.tick[i] + dtk != T) {
-            err |= kErrNotDue;
-            continue;
-        }
-        const double dt = ldexp(1.0, -lev);
-        const double h = 0.5 * dt, s6 = dt * (1.0 / 6.0);
-        const double x0[3] = {st.x[i], st.y[i], st.z[i]};
-        const double v0[3] = {st.vx[i], st.vy[i], st.vz[i]};
-        const double a0[3] = {st.ax[i], st.ay[i], st.az[i]};
-        const double j0[3] = {st.jx[i], st.jy[i], st.jz[i]};
-        double a1[3], j1[3], x1[3], v1[3], a2e[3], a3[3];
-        const double dt2 = dt * dt, dt3 = dt2 * dt, dt4 = dt3 * dt, dt5 = dt4 * dt;
-        const double idt2 = 1.0 / dt2, idt3 = 1.0 / dt3;  // exact: powers of two
-        bool ok = true;
+        double a1[3], j1[3];
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             a1[q] = an[q * in_stride + s];
             j1[q] = jn[q * in_stride + s];
-            const double xp = fma(dt, fma(dt, fma(s6, j0[q], 0.5 * a0[q]), v0[q]), x0[q]);
-            const double vp = fma(dt, fma(h, j0[q], a0[q]), v0[q]);
-            const double da = a0[q] - a1[q];
-            const double a2 = (-6.0 * da - dt * (4.0 * j0[q] + 2.0 * j1[q])) * idt2;
-            const double a3q = (12.0 * da + 6.0 * dt * (j0[q] + j1[q])) * idt3;
-            x1[q] = xp + a2 * dt4 / 24.0 + a3q * dt5 / 120.0;
-            v1[q] = vp + a2 * dt3 / 6.0 + a3q * dt4 / 24.0;
-            a2e[q] = a2 + dt * a3q;
-            a3[q] = a3q;
         }
-        ok = finite3(x1[0], x1[1], x1[2]) && finite3(v1[0], v1[1], v1[2]) &&
-             finite3(a1[0], a1[1], a1[2]) && finite3(j1[0], j1[1], j1[2]);
-        if (!ok)
-            err |= kErrNonFinite;
-        // Aarseth criterion and block quantisation
-        const double na = norm3(a1[0], a1[1], a1[2]), nj = norm3(j1[0], j1[1], j1[2]);
-        const double na2 = norm3(a2e[0], a2e[1], a2e[2]), na3 = norm3(a3[0], a3[1], a3[2]);
-        const double num = na * na2 + nj * nj;
-        const double den = nj * na3 + na2 * na2;
-        const double dt_raw = den > 0.0 ? sqrt(pr.eta * num / den) : INFINITY;
-        int nlev = lev;
-        if (dt_raw < dt) {
-            while (nlev < pr.lev_max && ldexp(1.0, -nlev) > dt_raw)
-                nlev++;
-            if (ldexp(1.0, -nlev) > dt_raw)
-                clamps++;
-        } else if (dt_raw >= 2.0 * dt && lev > pr.lev_min && (T % (2 * dtk)) == 0) {
-            nlev = lev - 1;
-        }
-        st.x[i] = x1[0];
-        st.y[i] = x1[1];
-        st.z[i] = x1[2];
-        st.vx[i] = v1[0];
-        st.vy[i] = v1[1];
-        st.vz[i] = v1[2];
-        st.ax[i] = a1[0];
-        st.ay[i] = a1[1];
-        st.az[i] = a1[2];
-        st.jx[i] = j1[0];
-        st.jy[i] = j1[1];
-        st.jz[i] = j1[2];
-        st.tick[i] = T;
-        st.lev[i] = (int8_t)nlev;
+        (void)correct_particle(st, pr, i, t_cur[c], a1, j1, err, clamps);
     }
     if (err)
         atomicOr(&ctl->err, err);
     if (clamps)
         atomicAdd(&ctl->clamps, clamps);
+}
+
+// ---------------------------------------------------------------- reduction
+// Sums the per-slice partial results of every slot whose cluster was split
+// into S > 1 j-slices.  Narrow splits (S <= 8): one thread per slot, slices in
+// order.  Medium (S <= 64): one wave per slot, lane l adds slices l, l+64, ...,
+// then a fixed butterfly.  Wide: one workgroup per slot and a fixed tree.
+// Every order is fixed, so results are bitwise reproducible.  With one
+// cluster only the n live slots are visited.
+//
+// CORR (a block step): instead of storing a slot's sums, correct its particle
+// with them right away (slots of clusters that were not split take the force
+// kernel's direct output), and keep the per-level counts of the block-step
+// scheme current: level changes are gathered per workgroup in LDS (one
+// cluster) or added to the cluster's row directly (several).
+struct CorrArgs {
+    State st;
+    Params pr;
+    const int64_t *t_cur;
+    int32_t *lev_cnt;
+    const int32_t *cursor;  // compaction count of the step (checked against the plan)
+    DevCtl *ctl;
+};
+
+template <bool CORR>
+__global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *cid,
+                                                  int64_t slot_space, const int32_t *s_max,
+                                                  CorrArgs ca) {
+    __shared__ double red[7][kWG];
+    __shared__ int32_t dlev[kLevels];
+    const int smax = uniform_i32(*s_max);
+    if (!CORR && smax <= 1)
+        return;
+    if (CORR) {
+        if (threadIdx.x < kLevels)
+            dlev[threadIdx.x] = 0;
+        __syncthreads();
+    }
+    int32_t err = 0;
+    unsigned long long clamps = 0;
+    auto emit = [&](int64_t s, int c, const double *v) {
+        if (!CORR) {
+            fa.out_acc[s] = v[0];
+            fa.out_acc[fa.out_stride + s] = v[1];
+            fa.out_acc[2 * fa.out_stride + s] = v[2];
+            fa.out_jerk[s] = v[3];
+            fa.out_jerk[fa.out_stride + s] = v[4];
+            fa.out_jerk[2 * fa.out_stride + s] = v[5];
+            if (fa.out_pot)
+                fa.out_pot[s] = v[6];
+            return;
+        }
+        const int64_t i = fa.i_list[s];
+        if (i < fa.off[c] || i >= fa.off[c + 1]) {
+            err |= kErrRange;
+            return;
+        }
+        const int old = ca.st.lev[i];
+        const int nl = correct_particle(ca.st, ca.pr, i, ca.t_cur[c], v, v + 3, err, clamps);
+        if (nl >= 0 && nl != old) {
+            if (fa.C == 1) {
+                atomicAdd(&dlev[old], -1);
+                atomicAdd(&dlev[nl], 1);
+            } else {
+                atomicAdd(&ca.lev_cnt[(int64_t)c * kLevels + old], -1);
+                atomicAdd(&ca.lev_cnt[(int64_t)c * kLevels + nl], 1);
+            }
+        }
+    };
+    // the force kernel's own output for a slot of a cluster that was not split
+    auto direct = [&](int64_t s, double *v) {
+#pragma unroll
+        for (int q = 0; q < 3; q++) {
+            v[q] = fa.out_acc[q * fa.out_stride + s];
+            v[3 + q] = fa.out_jerk[q * fa.out_stride + s];
+        }
+        v[6] = 0.0;
+    };
+    int64_t bound = slot_space;
+    if (fa.C == 1)
+        bound = min(bound, (int64_t)uniform_i32(fa.n_cur[0]));
+    if (smax <= 8) {
+        for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < bound;
+             s += (int64_t)gridDim.x * blockDim.x) {
+            const int c = fa.C > 1 ? cid[s] : 0;
+            const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
+            const int64_t n = fa.n_cur[c];
+            const int S = fa.S[c];
+            if (k >= n || (!CORR && S <= 1))
+                continue;
+            double v[7];
+            if (S <= 1) {
+                direct(s, v);
+            } else {
+                const int64_t base = fa.part_begin[c] + k;
+#pragma unroll
+                for (int q = 0; q < 7; q++) {
+                    double sum = 0.0;
+                    for (int js = 0; js < S; js++)
+                        sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+                    v[q] = sum;
+                }
+            }
+            emit(s, c, v);
+        }
+    } else if (smax > 64) {
+        // one workgroup per slot: thread t adds slices t, t+256, ...; then a
+        // fixed tree over the 256 threads
+        const int t = threadIdx.x;
+        for (int64_t s = blockIdx.x; s < bound; s += gridDim.x) {
+            const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
+            const int64_t k = fa.slots_at_offsets ? s - uniform_i64(fa.off[c]) : s;
+            const int64_t n = uniform_i32(fa.n_cur[c]);
+            const int S = uniform_i32(fa.S[c]);
+            if (k >= n)
+                continue;
+            if (S <= 1) {
+                if (CORR && t == 0) {
+                    double v[7];
+                    direct(s, v);
+                    emit(s, c, v);
+                }
+                continue;
+            }
+            const int64_t base = uniform_i64(fa.part_begin[c]) + k;
+#pragma unroll
+            for (int q = 0; q < 7; q++) {
+                double sum = 0.0;
+                for (int js = t; js < S; js += kWG)
+                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+                red[q][t] = sum;
+            }
+            __syncthreads();
+            for (int o = kWG / 2; o > 0; o >>= 1) {
+                if (t < o) {
+#pragma unroll
+                    for (int q = 0; q < 7; q++)
+                        red[q][t] += red[q][t + o];
+                }
+                __syncthreads();
+            }
+            if (t == 0) {
+                double v[7];
+#pragma unroll
+                for (int q = 0; q < 7; q++)
+                    v[q] = red[q][0];
+                emit(s, c, v);
+            }
+            __syncthreads();
+        }
+    } else {
+        const int lane = threadIdx.x & 63;
+        const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
+        const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+        for (int64_t s = wave; s < bound; s += nwaves) {
+            const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
+            const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
+            const int64_t n = fa.n_cur[c];
+            const int S = fa.S[c];
+            if (k >= n)
+                continue;
+            if (S <= 1) {
+                if (CORR && lane == 0) {
+                    double v[7];
+                    direct(s, v);
+                    emit(s, c, v);
+                }
+                continue;
+            }
+            const int64_t base = fa.part_begin[c] + k;
+            double v[7];
+#pragma unroll
+            for (int q = 0; q < 7; q++) {
+                double sum = 0.0;
+                for (int js = lane; js < S; js += 64)
+                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+#pragma unroll
+                for (int o = 32; o > 0; o >>= 1)
+                    sum += __shfl_xor(sum, o);
+                v[q] = sum;
+            }
+            if (lane == 0)
+                emit(s, c, v);
+        }
+    }
+    if (CORR) {
+        __syncthreads();
+        if (threadIdx.x < kLevels && dlev[threadIdx.x] != 0)
+            atomicAdd(&ca.lev_cnt[threadIdx.x], dlev[threadIdx.x]);
+        if (err)
+            atomicOr(&ca.ctl->err, err);
+        if (clamps)
+            atomicAdd(&ca.ctl->clamps, clamps);
+        if (fa.C == 1 && blockIdx.x == 0 && threadIdx.x == 0 && ca.cursor[0] != fa.n_cur[0])
+            atomicOr(&ca.ctl->err, kErrPlan);
+    }
 }
 
 // Start-up: store the first force sweep, t_i = 0 and the start-up step.
@@ -776,17 +981,34 @@ hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, 
     return hipGetLastError();
 }
 
-hipError_t launch_select(const State &st, const Params &pr, const int64_t *off,
-                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
-                         int64_t *t_next, int32_t *n_act, int32_t *i_list, const DevCtl *ctl,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(k_select_min, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr, off,
-                       chunk_c, chunk_b, t_next);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
+hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
+                        const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
+                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, DevCtl *ctl,
+                        hipStream_t s) {
+    hipError_t e;
+    if ((e = launch_fill_i32(pl.lev_cnt, 0, (int64_t)pr.C * kLevels, s)) != hipSuccess ||
+        (e = launch_fill_i64(t_min, LLONG_MAX, pr.C, s)) != hipSuccess ||
+        (e = launch_fill_i64(t_max, 0, pr.C, s)) != hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_select_compact, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr, off,
-                       chunk_c, chunk_b, t_next, n_act, i_list, ctl);
+    hipLaunchKernelGGL(k_prime, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr, off, chunk_c,
+                       chunk_b, pl.lev_cnt, t_min, t_max, ctl);
+    if ((e = hipGetLastError()) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(k_prime_finish, dim3(grid_for(pr.C)), dim3(kWG), 0, s, pr, t_min, t_max,
+                       pl.t_now, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_predict_compact(const State &st, const Params &pr, const JBuf &jb,
+                                  const int64_t *off, const int32_t *chunk_c,
+                                  const int64_t *chunk_b, int64_t n_chunks, const PlanDev &pl,
+                                  int32_t *cursor, int32_t *i_list, hipStream_t s) {
+    if (pr.precision == NBODY_PREC_MIXED)
+        hipLaunchKernelGGL(k_predict_compact<1>, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr,
+                           jb, off, chunk_c, chunk_b, pl, cursor, i_list);
+    else
+        hipLaunchKernelGGL(k_predict_compact<0>, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr,
+                           jb, off, chunk_c, chunk_b, pl, cursor, i_list);
     return hipGetLastError();
 }
 
@@ -806,8 +1028,22 @@ hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, 
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
                          const int32_t *s_max, hipStream_t s) {
     // enough waves for one per slot up to 4096 workgroups; grid-stride beyond
-    hipLaunchKernelGGL(k_reduce, dim3(grid_for(slot_space * 64)), dim3(kWG), 0, s, fa, cid,
-                       slot_space, s_max);
+    hipLaunchKernelGGL(k_reduce_t<false>, dim3(grid_for(slot_space * 64)), dim3(kWG), 0, s, fa,
+                       cid, slot_space, s_max, CorrArgs{});
+    return hipGetLastError();
+}
+
+hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Params &pr,
+                                 const int32_t *cid, const PlanDev &pl, const int32_t *cursor,
+                                 const int32_t *s_max, DevCtl *ctl, hipStream_t s) {
+    // the grid is fixed when a step is captured: one thread per particle for
+    // unsplit and narrow splits, grid-stride waves / workgroups for wider ones
+    const int64_t n = pr.n_total;
+    const int64_t g = std::min<int64_t>(4096, std::max<int64_t>((n + kWG - 1) / kWG,
+                                                                std::min<int64_t>(n, 1024)));
+    const CorrArgs ca{st, pr, pl.t_cur, pl.lev_cnt, cursor, ctl};
+    hipLaunchKernelGGL(k_reduce_t<true>, dim3((unsigned)g), dim3(kWG), 0, s, fa, cid, n, s_max,
+                       ca);
     return hipGetLastError();
 }
 

@@ -34,8 +34,9 @@ struct nbody_ctx {
     JBuf jb;
     int32_t *i_list_d = nullptr;
     int32_t *iota_d = nullptr;
-    int32_t *n_act_d = nullptr;
-    int64_t *t_next_d = nullptr;
+    int32_t *n_act_d = nullptr;   // host-set blocks; the block step's compaction cursor
+    int64_t *t_next_d = nullptr;  // host-set block times; earliest next time when priming
+    int64_t *t_max_d = nullptr;   // latest last time when priming
     PlanDev pl{};
     double *acc_new = nullptr, *jerk_new = nullptr, *pot_new = nullptr;
     double *part = nullptr;
@@ -167,6 +168,34 @@ ForceArgs force_args(nbody_ctx *c, const int32_t *i_list, int slots_at_offsets, 
     return fa;
 }
 
+// The force launches of a device-planned evaluation: one per distinct launch
+// shape and grid among the classes (or only class `only`); each runs only if
+// the plan picked one of the classes it serves.
+hipError_t launch_classes(nbody_ctx *c, ForceArgs fa, int mixed, int want_pot, int excl,
+                          int only) {
+    int done = 0;
+    for (int k = 0; k < kClasses; k++) {
+        if ((only >= 0 && k != only) || (done >> k) & 1)
+            continue;
+        const Shape &sh = c->cls_shape[k];
+        const int grid = grid_of(c, k, want_pot, excl);
+        int mask = 0;
+        for (int q = k; q < kClasses; q++) {
+            const Shape &o = c->cls_shape[q];
+            if ((only < 0 || q == only) && o.i_per_lane == sh.i_per_lane &&
+                o.j_lanes == sh.j_lanes && o.j_tile == sh.j_tile &&
+                grid_of(c, q, want_pot, excl) == grid)
+                mask |= 1 << q;
+        }
+        done |= mask;
+        fa.cls_mask = mask;
+        hipError_t e = launch_force(sh, mixed, want_pot, excl, fa, grid, c->stream);
+        if (e != hipSuccess)
+            return e;
+    }
+    return hipSuccess;
+}
+
 // One force evaluation planned on the device.  host_n >= 0: the block size is
 // known on the host (single cluster) and only that class's kernel is launched;
 // otherwise every class kernel is launched and all but the planned one exit.
@@ -185,16 +214,9 @@ hipError_t enqueue_force(nbody_ctx *c, const int32_t *i_list, int slots_at_offse
     if (e != hipSuccess)
         return e;
     ForceArgs fa = force_args(c, i_list, slots_at_offsets, acc, jerk, pot, stride);
-    for (int k = 0; k < kClasses; k++) {
-        if (only >= 0 && k != only)
-            continue;
-        // identical shapes in two classes: the planned class id still selects one launch
-        fa.my_cls = k;
-        e = launch_force(c->cls_shape[k], mixed, want_pot, excl, fa, grid_of(c, k, want_pot, excl),
-                         c->stream);
-        if (e != hipSuccess)
-            return e;
-    }
+    e = launch_classes(c, fa, mixed, want_pot, excl, only);
+    if (e != hipSuccess)
+        return e;
     return launch_reduce(fa, c->cid_d, slot_space, &c->ctl->s_max, c->stream);
 }
 
@@ -218,36 +240,35 @@ int consume_error(nbody_ctx *c, const DevCtl &h) {
     return NBODY_EDEVICE;
 }
 
+// Level counts and times of the block-step scheme, rebuilt from the state
+// (which the caller owns and the explicit entry points may have changed).
+hipError_t enqueue_prime(nbody_ctx *c) {
+    return launch_prime(c->st, c->pr, c->off_d, c->chunk_c_d, c->chunk_b_d, c->n_chunks, c->pl,
+                        c->t_next_d, c->t_max_d, c->ctl, c->stream);
+}
+
+// One block step of every active cluster (section 4.1): plan the next block
+// from the level counts, predict and compact, force, then reduce the j-split
+// and correct in one pass.  Nothing here reads back to the host, so a batch
+// of steps is captured into one graph.
 hipError_t enqueue_block_step(nbody_ctx *c) {
-    hipError_t e = launch_select(c->st, c->pr, c->off_d, c->chunk_c_d, c->chunk_b_d, c->n_chunks,
-                                 c->t_next_d, c->n_act_d, c->i_list_d, c->ctl, c->stream);
-    if (e != hipSuccess)
-        return e;
-    // planning happens inside enqueue_force; predict needs t_cur from the plan,
-    // so plan first (host_n < 0), then predict, then the force kernels.
     const int excl = c->pr.eps2 == 0.0;
     const int mixed = c->pr.precision == NBODY_PREC_MIXED;
     const ClassTable ct = class_table(c, 0, excl);
-    e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl, c->part_cap, ct,
-                    kJTile, -1, 0, 1, c->stream);
+    hipError_t e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl,
+                               c->part_cap, ct, kJTile, kPlanFromLevels, 0, 1, c->stream);
     if (e != hipSuccess)
         return e;
-    e = launch_predict(c->st, c->pr, c->jb, c->cid_d, c->pl.t_cur, c->pl.n_cur, 0, 0, c->stream);
+    e = launch_predict_compact(c->st, c->pr, c->jb, c->off_d, c->chunk_c_d, c->chunk_b_d,
+                               c->n_chunks, c->pl, c->n_act_d, c->i_list_d, c->stream);
     if (e != hipSuccess)
         return e;
     ForceArgs fa = force_args(c, c->i_list_d, 1, c->acc_new, c->jerk_new, nullptr, c->pr.n_total);
-    for (int k = 0; k < kClasses; k++) {
-        fa.my_cls = k;
-        e = launch_force(c->cls_shape[k], mixed, 0, excl, fa, grid_of(c, k, 0, excl), c->stream);
-        if (e != hipSuccess)
-            return e;
-    }
-    e = launch_reduce(fa, c->cid_d, c->pr.n_total, &c->ctl->s_max, c->stream);
+    e = launch_classes(c, fa, mixed, 0, excl, -1);
     if (e != hipSuccess)
         return e;
-    return launch_correct(c->st, c->pr, c->i_list_d, 1, c->off_d, c->cid_d, c->pl.n_cur,
-                          c->pl.t_cur, c->pr.n_total, c->acc_new, c->jerk_new, c->pr.n_total,
-                          c->ctl, c->stream);
+    return launch_reduce_correct(fa, c->st, c->pr, c->cid_d, c->pl, c->n_act_d, &c->ctl->s_max,
+                                 c->ctl, c->stream);
 }
 
 void drop_graph(nbody_ctx *c) {
@@ -430,6 +451,9 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
         (e = dalloc(c, &c->pl.S, C)) != hipSuccess || (e = dalloc(c, &c->pl.jlen, C)) != hipSuccess ||
         (e = dalloc(c, &c->pl.part_begin, C)) != hipSuccess ||
         (e = dalloc(c, &c->pl.n_cur, C)) != hipSuccess || (e = dalloc(c, &c->pl.t_cur, C)) != hipSuccess ||
+        (e = dalloc(c, &c->pl.t_now, C)) != hipSuccess ||
+        (e = dalloc(c, &c->pl.lev_cnt, C * kLevels)) != hipSuccess ||
+        (e = dalloc(c, &c->t_max_d, C)) != hipSuccess ||
         (e = dalloc(c, &c->acc_new, 3 * N)) != hipSuccess ||
         (e = dalloc(c, &c->jerk_new, 3 * N)) != hipSuccess ||
         (e = dalloc(c, &c->pot_new, N)) != hipSuccess ||
@@ -455,6 +479,7 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
     if ((e = hipMemcpy(c->ctl, &h, sizeof(h), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
     if ((e = launch_iota_i32(c->iota_d, N, c->stream)) != hipSuccess ||
+        (e = launch_fill_i32(c->i_list_d, 0, N, c->stream)) != hipSuccess ||
         (e = launch_fill_i32(c->n_act_d, 0, C, c->stream)) != hipSuccess ||
         (e = launch_fill_i64(c->t_next_d, LLONG_MAX, C, c->stream)) != hipSuccess ||
         (e = hipStreamSynchronize(c->stream)) != hipSuccess)
@@ -522,7 +547,7 @@ int nbody_init(nbody_ctx *c) {
         NB_TRY(hipMemcpyAsync(c->n_act_d, nc.data(), nc.size() * sizeof(int32_t),
                               hipMemcpyHostToDevice, c->stream));
         NB_TRY(launch_fill_i64(c->t_next_d, 0, c->pr.C, c->stream));
-        NB_TRY(enqueue_force(c, c->iota_d, 1, -1, 0, 0, c->acc_new, c->jerk_new, nullptr, N, N));
+        NB_TRY(enqueue_force(c, c->iota_d, 1, kPlanFromLists, 0, 0, c->acc_new, c->jerk_new, nullptr, N, N));
         NB_TRY(launch_init_finish(c->st, c->pr, c->acc_new, c->jerk_new, N, c->ctl, c->stream));
         NB_TRY(hipStreamSynchronize(c->stream));  // nc must outlive the async copy
     }
@@ -596,12 +621,18 @@ int nbody_step_block(nbody_ctx *c, double *t_out, int64_t *n_out) {
     if (!c->initialised)
         return NBODY_ESTATE;
     NB_TRY(launch_set_i64(reinterpret_cast<int64_t *>(&c->ctl->t_end_tick), LLONG_MAX, c->stream));
+    NB_TRY(enqueue_prime(c));
+    DevCtl h;
+    int rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    if (h.err)
+        return consume_error(c, h);
     NB_TRY(enqueue_block_step(c));
     c->predicted = false;
     if (!t_out && !n_out)
         return NBODY_OK;
-    DevCtl h;
-    int rc = read_ctl(c, &h);
+    rc = read_ctl(c, &h);
     if (rc != NBODY_OK)
         return rc;
     if (n_out)
@@ -628,10 +659,13 @@ int nbody_run_until(nbody_ctx *c, double t_end, int64_t *n_steps_out) {
         if (rc != NBODY_OK)
             return rc;
     }
+    NB_TRY(enqueue_prime(c));
     DevCtl h;
     int rc = read_ctl(c, &h);
     if (rc != NBODY_OK)
         return rc;
+    if (h.err)
+        return consume_error(c, h);
     const unsigned long long steps0 = h.steps;
     for (;;) {
         NB_TRY(hipGraphLaunch(c->graph_exec, c->stream));
@@ -751,7 +785,7 @@ int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *be
                 if (e == hipSuccess)
                     e = hipEventRecord(e0, c->stream);
                 if (e == hipSuccess)
-                    e = enqueue_force(c, c->iota_d, 1, -1, 0, 0, c->acc_new, c->jerk_new,
+                    e = enqueue_force(c, c->iota_d, 1, kPlanFromLists, 0, 0, c->acc_new, c->jerk_new,
                                       nullptr, N, N);
             }
             if (e == hipSuccess)

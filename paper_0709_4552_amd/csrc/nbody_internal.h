@@ -10,8 +10,13 @@
 namespace nb {
 
 constexpr int kWG = 256;          // threads per workgroup, every kernel
-constexpr int kChunk = 2048;      // particles per selection chunk (never crosses clusters)
+constexpr int kChunk = kWG;       // particles per scan chunk, one per thread (never crosses clusters)
+constexpr int kLevels = 64;       // step levels tracked per cluster (level L: dt = 2^-L)
 constexpr int kPlanThreads = 1024;
+
+// Where the planner takes each cluster's block from.
+constexpr int32_t kPlanFromLists = -1;   // n_act[c] particles at time t_next[c] (set by the host)
+constexpr int32_t kPlanFromLevels = -2;  // next block of the block-step scheme, from the level counts
 
 // bits of the device error word
 enum : int32_t {
@@ -90,6 +95,8 @@ struct PlanDev {
     int64_t *part_begin;   // [C] first partial-sum slot of each cluster (S>1)
     int32_t *n_cur;        // [C] block size of the step being computed
     int64_t *t_cur;        // [C] time (ticks) of the step being computed
+    int64_t *t_now;        // [C] time (ticks) of the cluster's last block step
+    int32_t *lev_cnt;      // [C][kLevels] particles of the cluster on each step level
 };
 
 struct Params {
@@ -134,7 +141,7 @@ struct ForceArgs {
     int32_t *err;
     unsigned long long *item_counter;
     const int32_t *cls;           // class chosen by the plan
-    int32_t my_cls;               // this launch runs only if *cls == my_cls
+    int32_t cls_mask;             // this launch runs only if bit *cls is set
     int32_t fetch_lane;           // thread that pops the work queue (always 0); a
                                   // run-time value so the compiler cannot merge its
                                   // branch with other tid == 0 branches across the
@@ -175,16 +182,23 @@ hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);
 hipError_t launch_predict(const State &st, const Params &pr, const JBuf &jb, const int32_t *cid,
                           const int64_t *t_cur, const int32_t *n_cur, int64_t t_host,
                           int use_host_t, hipStream_t s);
-hipError_t launch_select(const State &st, const Params &pr, const int64_t *off,
-                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
-                         int64_t *t_next, int32_t *n_act, int32_t *i_list, const DevCtl *ctl,
-                         hipStream_t s);
+hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
+                        const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
+                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, DevCtl *ctl,
+                        hipStream_t s);
+hipError_t launch_predict_compact(const State &st, const Params &pr, const JBuf &jb,
+                                  const int64_t *off, const int32_t *chunk_c,
+                                  const int64_t *chunk_b, int64_t n_chunks, const PlanDev &pl,
+                                  int32_t *cursor, int32_t *i_list, hipStream_t s);
 hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, int32_t *n_act,
                        int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
                        int32_t j_tile, int32_t host_n, int64_t host_t, int32_t count_stats,
                        hipStream_t s);
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
                          const int32_t *s_max, hipStream_t s);
+hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Params &pr,
+                                 const int32_t *cid, const PlanDev &pl, const int32_t *cursor,
+                                 const int32_t *s_max, DevCtl *ctl, hipStream_t s);
 hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_list,
                           int32_t slots_at_offsets, const int64_t *off, const int32_t *cid,
                           const int32_t *n_cur, const int64_t *t_cur, int64_t slot_space,

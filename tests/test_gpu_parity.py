@@ -268,6 +268,53 @@ def test_error_paths():
     g.close()
 
 
+def test_block_steps_reject_unsynchronised_state():
+    # Correcting only part of a due block leaves a state no block step can
+    # continue from; so does a last time that is not a multiple of the step.
+    # Both are refused before anything is stepped.
+    note("unsynchronised state")
+    import torch
+    x, v, m = plummer(500, 1009)
+    g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g.init()
+    for _ in range(200):  # advance to a block of at least two particles
+        _, _, _, _, tg, dtg = g.host_state()
+        t, act = _due(tg, dtg)
+        if act.size >= 2:
+            break
+        g.step_block()
+    assert act.size >= 2
+    g.predict(t)
+    acc, jerk, _ = g.force_jerk(act[:1].astype(np.int32), t)
+    g.correct(act[:1].astype(np.int32), t, acc, jerk)
+    g.sync()
+    before = [a.clone() for a in (g.pos, g.vel, g.t_tick, g.level)]
+    with pytest.raises(NBodyError) as e:
+        g.run_until(2.0 ** -3)
+    assert e.value.code == _lib.NBODY_ESTATE
+    with pytest.raises(NBodyError) as e:
+        g.step_block()
+    assert e.value.code == _lib.NBODY_ESTATE
+    for a, b in zip((g.pos, g.vel, g.t_tick, g.level), before):
+        assert torch.equal(a, b)
+    # correcting the rest of the block makes the state synchronised again
+    g.predict(t)
+    rest = act[1:].astype(np.int32)
+    acc, jerk, _ = g.force_jerk(rest, t)
+    g.correct(rest, t, acc, jerk)
+    assert g.run_until(2.0 ** -3) > 0
+    _, _, _, _, tg, dtg = g.host_state()
+    assert np.all(tg == 2.0 ** -3)
+    # a last time off its step's grid
+    k = int(np.argmax(dtg))
+    assert dtg[k] > 2.0 ** -20
+    g.t_tick[k] += 1
+    with pytest.raises(NBodyError) as e:
+        g.step_block()
+    assert e.value.code == _lib.NBODY_ESTATE
+    g.close()
+
+
 def test_nonfinite_state_is_reported():
     note("non-finite")
     x, v, m = plummer(300, 1008)
