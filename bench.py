@@ -38,8 +38,8 @@ SEED = 1003
 # HBM traffic of the full-sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by the
 # same counters on an elementwise kernel of known size; valid only for the kernel source it was
 # measured on (checked by hash, else "traffic" is reported as null).
-SWEEP_TRAFFIC = {"force_source_sha256_prefix": "d629d004d94c7f9b", "read_bytes": 153.8e6,
-                 "write_bytes": 55.2e6}
+SWEEP_TRAFFIC = {"force_source_sha256_prefix": "9b7a884693366dfe", "read_bytes": 142.0e6,
+                 "write_bytes": 66.2e6}
 
 
 def sweep_traffic():
