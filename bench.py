@@ -346,7 +346,7 @@ def main():
                          "copy of known size (for hardware-counter runs); prints one JSON line")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+        print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(how the path would shard is described in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
 

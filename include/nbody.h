@@ -56,7 +56,7 @@ extern "C" {
 #define NBODY_ENOMEM (-3)       /* device allocation failed                      */
 #define NBODY_EDEVICE (-4)      /* HIP runtime error                             */
 #define NBODY_ENONFINITE (-5)   /* the device produced a non-finite value        */
-#define NBODY_EUNSUPPORTED (-6) /* valid but not supported by this build         */
+#define NBODY_EUNSUPPORTED (-6) /* valid but not supported by this library       */
 #define NBODY_ERANGE (-7)       /* the device met a particle index out of range  */
 
 /* arithmetic of the pairwise force sum */
