@@ -701,10 +701,13 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
 // ---------------------------------------------------------------- reduction
 // Sums the per-slice partial results of every slot whose cluster was split
 // into S > 1 j-slices.  Narrow splits (S <= 8): one thread per slot, slices in
-// order.  Medium (S <= 64): one wave per slot, lane l adds slices l, l+64, ...,
-// then a fixed butterfly.  Wide: one workgroup per slot and a fixed tree.
-// Every order is fixed, so results are bitwise reproducible.  With one
-// cluster only the n live slots are visited.
+// order.  Wider: one workgroup per slot (thread t adds slices t, t+256, ...,
+// then a fixed tree) while there are no more slots than workgroups, else one
+// wave per slot (lane l adds slices l, l+64, ..., then a fixed butterfly), so
+// no workgroup walks through many slots behind barriers.  (Without the slot
+// count, for ensembles outside a block step, splits wider than 64 take a
+// workgroup.)  Every order is fixed, so results are bitwise reproducible for a
+// given plan.  With one cluster only the n live slots are visited.
 //
 // CORR (a block step): instead of storing a slot's sums, correct its particle
 // with them right away (slots of clusters that were not split take the force
@@ -777,6 +780,12 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
     int64_t bound = slot_space;
     if (fa.C == 1)
         bound = min(bound, (int64_t)uniform_i32(fa.n_cur[0]));
+    int64_t n_tot = -1;  // active slots of the plan, where known
+    if (fa.C == 1)
+        n_tot = bound;
+    else if (CORR)
+        n_tot = uniform_i32(ca.ctl->n_last);
+    const bool wg_mode = n_tot >= 0 ? n_tot <= (int64_t)gridDim.x : smax > 64;
     if (smax <= 8) {
         for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < bound;
              s += (int64_t)gridDim.x * blockDim.x) {
@@ -801,7 +810,7 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
             }
             emit(s, c, v);
         }
-    } else if (smax > 64) {
+    } else if (wg_mode) {
         // one workgroup per slot: thread t adds slices t, t+256, ...; then a
         // fixed tree over the 256 threads
         const int t = threadIdx.x;
