@@ -58,6 +58,7 @@ extern "C" {
 #define NBODY_ENONFINITE (-5)   /* the device produced a non-finite value        */
 #define NBODY_EUNSUPPORTED (-6) /* valid but not supported by this library       */
 #define NBODY_ERANGE (-7)       /* the device met a particle index out of range  */
+#define NBODY_EIO (-8)          /* checkpoint file not writable / readable / valid */
 
 /* arithmetic of the pairwise force sum */
 #define NBODY_PREC_FP64 0  /* every operation in FP64                             */
@@ -227,6 +228,32 @@ int nbody_step_block(nbody_ctx *ctx, double *t_out, int64_t *n_out);
  * receives the number of ensemble block steps that did work.
  */
 int nbody_run_until(nbody_ctx *ctx, double t_end, int64_t *n_steps_out);
+
+/*
+ * Checkpoint and resume of a long integration (section 4.1: the run is a loop
+ * of block steps over caller-owned state, so the state plus the context's
+ * configuration is everything a run needs to continue).
+ *
+ * nbody_save synchronises, then writes to `path` (host file name): the
+ * configuration (n_total, clusters and their offsets, eps, eta, eta_init, the
+ * step range, precision), the statistics, the tuning table, and the particle
+ * state (pos, vel, acc, jerk, mass as FP64; t_tick; level).  Little-endian
+ * binary with a version and a 64-bit checksum; written to "<path>.part" and
+ * renamed, so an existing file is only ever replaced by a complete one.
+ * ESTATE before nbody_init; a pending device error is reported instead of
+ * saving; EIO if the file cannot be written.
+ *
+ * nbody_load reads such a file into a context created with the same
+ * configuration (EINVAL otherwise; nbody_init is not needed) and copies the
+ * state into the caller's state arrays, replacing their contents; statistics
+ * and tuning continue from the file.  EIO if the file cannot be read, is not a
+ * checkpoint of this version, is truncated or fails its checksum; nothing is
+ * changed then.  A run continued from a checkpoint on the same device takes
+ * the same block steps and gives bitwise the same state as one that was not
+ * interrupted.  Synchronises.
+ */
+int nbody_save(nbody_ctx *ctx, const char *path);
+int nbody_load(nbody_ctx *ctx, const char *path);
 
 /* Wait for the context's work and report (then clear) the device error word. */
 int nbody_sync(nbody_ctx *ctx);

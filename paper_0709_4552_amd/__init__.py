@@ -168,6 +168,15 @@ class NBody:
         return ({"size_class": t.size_class, "i_per_lane": t.i_per_lane, "j_lanes": t.j_lanes,
                  "j_tile": t.j_tile, "grid": t.grid}, ms)
 
+    def save(self, path: str):
+        """Checkpoint: configuration, statistics, tuning and particle state."""
+        check(_lib.nbody_save(self.ctx, str(path)), "nbody_save")
+
+    def load(self, path: str):
+        """Resume from a checkpoint of a context with the same configuration;
+        the state tensors are overwritten (nbody_init is not needed)."""
+        check(_lib.nbody_load(self.ctx, str(path)), "nbody_load")
+
     # --- host views (copies) ------------------------------------------------
     def host_state(self):
         """(x, v, a, jerk) as float64 (N, 3) numpy arrays, t (N,) and dt (N,)."""

@@ -20,6 +20,7 @@ NBODY_EDEVICE = -4
 NBODY_ENONFINITE = -5
 NBODY_EUNSUPPORTED = -6
 NBODY_ERANGE = -7
+NBODY_EIO = -8
 
 NBODY_PREC_FP64 = 0
 NBODY_PREC_MIXED = 1
@@ -29,7 +30,7 @@ EXPORTS = (
     "nbody_strerror", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
     "nbody_force_jerk", "nbody_correct", "nbody_step_block", "nbody_run_until", "nbody_sync",
     "nbody_get_stats", "nbody_read_predicted", "nbody_get_tuning", "nbody_set_tuning",
-    "nbody_autotune",
+    "nbody_autotune", "nbody_save", "nbody_load",
 )
 
 
@@ -117,6 +118,8 @@ def load(path: str = LIB_PATH):
     L.nbody_get_tuning.argtypes = [vp, ctypes.POINTER(nbody_tuning)]
     L.nbody_set_tuning.argtypes = [vp, ctypes.POINTER(nbody_tuning)]
     L.nbody_autotune.argtypes = [vp, i64, ctypes.POINTER(nbody_tuning), ctypes.POINTER(d)]
+    L.nbody_save.argtypes = [vp, ctypes.c_char_p]
+    L.nbody_load.argtypes = [vp, ctypes.c_char_p]
     for name in EXPORTS:
         if name != "nbody_strerror":
             getattr(L, name).restype = i32
@@ -215,3 +218,11 @@ def nbody_autotune(ctx: int, n_probe: int):
     rc = load().nbody_autotune(ctypes.c_void_p(ctx), int(n_probe), ctypes.byref(t),
                                ctypes.byref(ms))
     return rc, t, ms.value
+
+
+def nbody_save(ctx: int, path: str) -> int:
+    return load().nbody_save(ctypes.c_void_p(ctx), os.fsencode(path))
+
+
+def nbody_load(ctx: int, path: str) -> int:
+    return load().nbody_load(ctypes.c_void_p(ctx), os.fsencode(path))

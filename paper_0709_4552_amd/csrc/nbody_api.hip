@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <string>
 #include <vector>
 
 #include "nbody.h"
@@ -18,6 +19,7 @@ using namespace nb;
 
 struct nbody_ctx {
     Params pr{};
+    double eps = 0.0;  // as given (pr holds eps^2)
     State st{};
     hipStream_t stream = nullptr;
     int device = 0;
@@ -271,6 +273,83 @@ hipError_t enqueue_block_step(nbody_ctx *c) {
                                  c->ctl, c->stream);
 }
 
+// Largest |mass| of each cluster (the near-field threshold of the mixed form
+// uses it), from a host copy of the masses.
+hipError_t upload_mass_max(nbody_ctx *c, const double *mh) {
+    std::vector<float> mx(c->pr.C, 0.f);
+    for (int k = 0; k < c->pr.C; k++) {
+        double v = 0.0;
+        for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++)
+            v = std::max(v, std::fabs(mh[i]));
+        mx[k] = (float)v;
+    }
+    return hipMemcpy(c->mmax_d, mx.data(), mx.size() * sizeof(float), hipMemcpyHostToDevice);
+}
+
+// ---- checkpoint file ----
+// Little-endian binary: magic, version, the context's configuration (checked on
+// load), statistics, tuning table, then the particle state as 13 FP64 arrays
+// (x y z vx vy vz ax ay az jx jy jz m), int64 ticks and int8 levels, and an
+// FNV-1a 64-bit checksum of everything after the magic.
+constexpr char kCkptMagic[8] = {'N', 'B', 'O', 'D', 'Y', 'C', 'K', 'P'};
+constexpr uint32_t kCkptVersion = 1;
+
+struct Fnv {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void *p, size_t n) {
+        const unsigned char *b = static_cast<const unsigned char *>(p);
+        for (size_t i = 0; i < n; i++) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    }
+};
+
+struct CkptWriter {
+    FILE *f;
+    Fnv sum;
+    bool ok = true;
+    void put(const void *p, size_t n) {
+        if (ok && std::fwrite(p, 1, n, f) != n)
+            ok = false;
+        sum.add(p, n);
+    }
+};
+
+struct CkptReader {
+    FILE *f;
+    Fnv sum;
+    bool ok = true;
+    void get(void *p, size_t n) {
+        if (ok && std::fread(p, 1, n, f) != n)
+            ok = false;
+        if (ok)
+            sum.add(p, n);
+    }
+};
+
+// The configuration part of the header, in file order.
+struct CkptConfig {
+    int64_t n_total;
+    int32_t n_clusters;
+    int32_t precision;
+    double eps, eta, eta_init;
+    int32_t dt_min_log2, dt_max_log2;
+};
+
+CkptConfig ckpt_config(const nbody_ctx *c) {
+    CkptConfig k{};
+    k.n_total = c->pr.n_total;
+    k.n_clusters = c->pr.C;
+    k.precision = c->pr.precision;
+    k.eps = c->eps;
+    k.eta = c->pr.eta;
+    k.eta_init = c->pr.eta_init;
+    k.dt_min_log2 = c->pr.dt_min_log2;
+    k.dt_max_log2 = c->pr.dt_max_log2;
+    return k;
+}
+
 void drop_graph(nbody_ctx *c) {
     if (c->graph_exec)
         (void)hipGraphExecDestroy(c->graph_exec);
@@ -326,6 +405,7 @@ const char *nbody_strerror(int status) {
         case NBODY_ENONFINITE: return "non-finite value produced";
         case NBODY_EUNSUPPORTED: return "unsupported";
         case NBODY_ERANGE: return "particle index out of range";
+        case NBODY_EIO: return "checkpoint file could not be written or read, or is damaged";
         default: return "unknown status";
     }
 }
@@ -376,6 +456,7 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
     Params &pr = c->pr;
     pr.n_total = p->n_total;
     pr.C = p->n_clusters;
+    c->eps = p->eps;
     pr.eps2 = p->eps * p->eps;
     pr.eps2f = (float)pr.eps2;
     pr.eta = p->eta;
@@ -525,19 +606,11 @@ int nbody_init(nbody_ctx *c) {
     std::vector<int32_t> nc(c->pr.C);
     for (int k = 0; k < c->pr.C; k++)
         nc[k] = (int32_t)(c->off_h[k + 1] - c->off_h[k]);
-    // largest mass per cluster (near-field threshold of the mixed form)
     {
         std::vector<double> mh(N);
         NB_TRY(hipStreamSynchronize(c->stream));
         NB_TRY(hipMemcpy(mh.data(), c->st.m, N * sizeof(double), hipMemcpyDeviceToHost));
-        std::vector<float> mx(c->pr.C, 0.f);
-        for (int k = 0; k < c->pr.C; k++) {
-            double v = 0.0;
-            for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++)
-                v = std::max(v, std::fabs(mh[i]));
-            mx[k] = (float)v;
-        }
-        NB_TRY(hipMemcpy(c->mmax_d, mx.data(), mx.size() * sizeof(float), hipMemcpyHostToDevice));
+        NB_TRY(upload_mass_max(c, mh.data()));
     }
     // mixed: a first sweep without near field gives |a| for the thresholds
     const int passes = c->pr.precision == NBODY_PREC_MIXED ? 2 : 1;
@@ -836,6 +909,190 @@ int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *be
     if (rc != NBODY_OK)
         return rc;
     return consume_error(c, h);
+}
+
+int nbody_save(nbody_ctx *c, const char *path) {
+    if (!c || !path)
+        return NBODY_EINVAL;
+    if (!c->initialised)
+        return NBODY_ESTATE;
+    DevCtl h;
+    int rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    if (h.err)
+        return consume_error(c, h);
+    const int64_t N = c->pr.n_total;
+    const State &st = c->st;
+    const double *src[13] = {st.x,  st.y,  st.z,  st.vx, st.vy, st.vz, st.ax,
+                             st.ay, st.az, st.jx, st.jy, st.jz, st.m};
+    std::vector<double> buf;
+    std::vector<int64_t> tick;
+    std::vector<int8_t> lev;
+    try {
+        buf.resize(13 * (size_t)N);
+        tick.resize(N);
+        lev.resize(N);
+    } catch (const std::bad_alloc &) {
+        return NBODY_ENOMEM;
+    }
+    for (int q = 0; q < 13; q++)
+        NB_TRY(hipMemcpy(buf.data() + q * N, src[q], N * sizeof(double), hipMemcpyDeviceToHost));
+    NB_TRY(hipMemcpy(tick.data(), st.tick, N * sizeof(int64_t), hipMemcpyDeviceToHost));
+    NB_TRY(hipMemcpy(lev.data(), st.lev, N * sizeof(int8_t), hipMemcpyDeviceToHost));
+
+    // write beside the target, then rename: an existing checkpoint is replaced
+    // only by a complete one
+    const std::string tmp = std::string(path) + ".part";
+    FILE *f = std::fopen(tmp.c_str(), "wb");
+    if (!f)
+        return NBODY_EIO;
+    CkptWriter w{f};
+    if (std::fwrite(kCkptMagic, 1, sizeof(kCkptMagic), f) != sizeof(kCkptMagic))
+        w.ok = false;
+    const CkptConfig k = ckpt_config(c);
+    w.put(&kCkptVersion, sizeof(kCkptVersion));
+    w.put(&k.n_total, 8);
+    w.put(&k.n_clusters, 4);
+    w.put(&k.precision, 4);
+    w.put(&k.eps, 8);
+    w.put(&k.eta, 8);
+    w.put(&k.eta_init, 8);
+    w.put(&k.dt_min_log2, 4);
+    w.put(&k.dt_max_log2, 4);
+    w.put(c->off_h.data(), (c->off_h.size()) * sizeof(int64_t));
+    const uint64_t stats[3] = {h.steps, h.updates, h.clamps};
+    w.put(stats, sizeof(stats));
+    w.put(&h.interactions, sizeof(double));
+    for (int q = 0; q < kClasses; q++) {
+        const int32_t t[4] = {c->cls_shape[q].i_per_lane, c->cls_shape[q].j_lanes,
+                              c->cls_shape[q].j_tile, c->cls_grid[q]};
+        w.put(t, sizeof(t));
+    }
+    w.put(buf.data(), buf.size() * sizeof(double));
+    w.put(tick.data(), tick.size() * sizeof(int64_t));
+    w.put(lev.data(), lev.size());
+    const uint64_t sum = w.sum.h;
+    if (w.ok && std::fwrite(&sum, 1, sizeof(sum), f) != sizeof(sum))
+        w.ok = false;
+    if (std::fclose(f) != 0)
+        w.ok = false;
+    if (w.ok && std::rename(tmp.c_str(), path) != 0)
+        w.ok = false;
+    if (!w.ok) {
+        (void)std::remove(tmp.c_str());
+        return NBODY_EIO;
+    }
+    return NBODY_OK;
+}
+
+int nbody_load(nbody_ctx *c, const char *path) {
+    if (!c || !path)
+        return NBODY_EINVAL;
+    FILE *f = std::fopen(path, "rb");
+    if (!f)
+        return NBODY_EIO;
+    auto done = [&](int rc) {
+        std::fclose(f);
+        return rc;
+    };
+    char magic[sizeof(kCkptMagic)];
+    if (std::fread(magic, 1, sizeof(magic), f) != sizeof(magic) ||
+        std::memcmp(magic, kCkptMagic, sizeof(magic)) != 0)
+        return done(NBODY_EIO);
+    CkptReader r{f};
+    uint32_t ver = 0;
+    r.get(&ver, sizeof(ver));
+    if (!r.ok || ver != kCkptVersion)
+        return done(NBODY_EIO);
+    CkptConfig k{};
+    r.get(&k.n_total, 8);
+    r.get(&k.n_clusters, 4);
+    r.get(&k.precision, 4);
+    r.get(&k.eps, 8);
+    r.get(&k.eta, 8);
+    r.get(&k.eta_init, 8);
+    r.get(&k.dt_min_log2, 4);
+    r.get(&k.dt_max_log2, 4);
+    if (!r.ok)
+        return done(NBODY_EIO);
+    const CkptConfig mine = ckpt_config(c);
+    // a checkpoint of another configuration: refuse before reading further
+    if (k.n_total != mine.n_total || k.n_clusters != mine.n_clusters ||
+        k.precision != mine.precision || k.eps != mine.eps || k.eta != mine.eta ||
+        k.eta_init != mine.eta_init || k.dt_min_log2 != mine.dt_min_log2 ||
+        k.dt_max_log2 != mine.dt_max_log2)
+        return done(NBODY_EINVAL);
+    std::vector<int64_t> off(c->off_h.size());
+    r.get(off.data(), off.size() * sizeof(int64_t));
+    if (!r.ok)
+        return done(NBODY_EIO);
+    if (off != c->off_h)
+        return done(NBODY_EINVAL);
+    uint64_t stats[3];
+    double interactions = 0.0;
+    r.get(stats, sizeof(stats));
+    r.get(&interactions, sizeof(double));
+    Shape shape[kClasses];
+    int32_t grid[kClasses];
+    for (int q = 0; q < kClasses; q++) {
+        int32_t t[4] = {0, 0, 0, 0};
+        r.get(t, sizeof(t));
+        shape[q] = Shape{t[0], t[1], t[2]};
+        grid[q] = t[3];
+    }
+    const int64_t N = c->pr.n_total;
+    std::vector<double> buf;
+    std::vector<int64_t> tick;
+    std::vector<int8_t> lev;
+    try {
+        buf.resize(13 * (size_t)N);
+        tick.resize(N);
+        lev.resize(N);
+    } catch (const std::bad_alloc &) {
+        return done(NBODY_ENOMEM);
+    }
+    r.get(buf.data(), buf.size() * sizeof(double));
+    r.get(tick.data(), tick.size() * sizeof(int64_t));
+    r.get(lev.data(), lev.size());
+    uint64_t stored = 0;
+    if (!r.ok || std::fread(&stored, 1, sizeof(stored), f) != sizeof(stored) ||
+        stored != r.sum.h || std::fgetc(f) != EOF)
+        return done(NBODY_EIO);
+    for (int q = 0; q < kClasses; q++)
+        if (!force_shape_supported(shape[q]) || grid[q] < 0)
+            return done(NBODY_EIO);
+    std::fclose(f);
+
+    // everything read and checked: only now overwrite the caller's state
+    State &st = c->st;
+    double *dst[13] = {st.x, st.y, st.z, st.vx, st.vy, st.vz, st.ax, st.ay, st.az,
+                       st.jx, st.jy, st.jz, st.m};
+    NB_TRY(hipStreamSynchronize(c->stream));
+    for (int q = 0; q < 13; q++)
+        NB_TRY(hipMemcpy(dst[q], buf.data() + q * N, N * sizeof(double), hipMemcpyHostToDevice));
+    NB_TRY(hipMemcpy(st.tick, tick.data(), N * sizeof(int64_t), hipMemcpyHostToDevice));
+    NB_TRY(hipMemcpy(st.lev, lev.data(), N * sizeof(int8_t), hipMemcpyHostToDevice));
+    NB_TRY(upload_mass_max(c, buf.data() + 12 * N));
+    DevCtl h;
+    int rc = read_ctl(c, &h);
+    if (rc != NBODY_OK)
+        return rc;
+    h.err = 0;
+    h.steps = stats[0];
+    h.updates = stats[1];
+    h.clamps = stats[2];
+    h.interactions = interactions;
+    NB_TRY(hipMemcpy(c->ctl, &h, sizeof(h), hipMemcpyHostToDevice));
+    for (int q = 0; q < kClasses; q++) {
+        c->cls_shape[q] = shape[q];
+        c->cls_grid[q] = grid[q];
+    }
+    std::memset(c->occ_cache, 0, sizeof(c->occ_cache));
+    drop_graph(c);
+    c->initialised = true;
+    c->predicted = false;
+    return NBODY_OK;
 }
 
 }  // extern "C"

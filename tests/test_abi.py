@@ -38,7 +38,7 @@ def test_struct_layouts_match_header():
 
 
 def test_strerror_names_every_code():
-    for code in range(0, -8, -1):
+    for code in range(0, -9, -1):
         assert _lib.strerror(code) != "unknown status"
     assert _lib.strerror(-99) == "unknown status"
 
@@ -108,3 +108,5 @@ def test_null_context_is_rejected():
     assert L.nbody_predict(None, 0.0) == _lib.NBODY_EINVAL
     assert L.nbody_sync(None) == _lib.NBODY_EINVAL
     assert L.nbody_destroy(None) == _lib.NBODY_EINVAL
+    assert L.nbody_save(None, b"/tmp/x") == _lib.NBODY_EINVAL
+    assert L.nbody_load(None, b"/tmp/x") == _lib.NBODY_EINVAL

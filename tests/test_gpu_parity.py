@@ -371,7 +371,21 @@ def test_config2_block_steps_to_t1_energy(prec):
     eps = 1 / 256
     g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
     g.init()
-    steps = g.run_until(1.0)
+    # force error at the synchronised checkpoints t = 1/4 ... 1: the GPU sweep
+    # of all particles against the oracle on the same state
+    tol = 1e-6 if prec == NBODY_PREC_MIXED else 1e-11
+    everyone = np.arange(16384, dtype=np.int32)
+    steps = 0
+    for t in (0.25, 0.5, 0.75, 1.0):
+        steps += g.run_until(t)
+        xg, vg, _, _, tg, _ = g.host_state()
+        assert np.all(tg == t)
+        g.predict(t)
+        acc, jerk, _ = g.force_jerk(everyone, t, want_pot=False)
+        ra, rj, _ = oracle.force(xg, vg, m, eps, everyone)
+        ea = np.linalg.norm(acc.T.cpu().numpy() - ra, axis=1) / np.linalg.norm(ra, axis=1)
+        note(f"  t={t}: max rel acc err {ea.max():.2e}")
+        assert ea.max() <= tol
     xg, vg, _, _, tg, dtg = g.host_state()
     assert np.all(tg == 1.0)
     lv = -np.log2(dtg)
