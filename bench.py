@@ -19,6 +19,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import statistics
 import math
 import os
 import sys
@@ -158,16 +159,21 @@ def cpu_baseline(x, v, m, sweep_acc, budget_s: float):
     per_i = dt / probe.size
     k = int(min(n, max(256, budget_s / max(per_i, 1e-9))))
     r = np.linalg.norm(x, axis=1)
-    # the sample: the most central particles (hardest cancellation) + random ones
-    sample = np.unique(np.concatenate([np.argsort(r)[:min(512, k // 4)],
-                                       rng.integers(0, n, k)]))[:k]
+    if k >= n:
+        sample = np.arange(n)
+        what = "all"
+    else:
+        # the most central particles (hardest cancellation) + random ones
+        sample = np.unique(np.concatenate([np.argsort(r)[:min(512, k // 4)],
+                                           rng.integers(0, n, k)]))[:k]
+        what = f"the {min(512, k // 4)} most central + random"
     t0 = time.perf_counter()
     ra, rj, rp = oracle.force(x, v, m, EPS, sample)
     dt = time.perf_counter() - t0
     rate = sample.size * float(n) / dt
     out = {"value": rate, "unit": "interactions/s", "cores": oracle.threads(), "kind": "oracle",
-           "sample": f"oracle acc+jerk+pot of {sample.size} particles (the {min(512, k // 4)} most "
-                     f"central + random) against all N={n}, FP64, {dt:.1f} s"}
+           "sample": f"oracle acc+jerk+pot of {sample.size} particles ({what}) against all "
+                     f"N={n}, FP64, {dt:.1f} s"}
     errs = {}
     for name, (a, j) in sweep_acc.items():
         ea = np.linalg.norm(a[sample] - ra, axis=1) / np.linalg.norm(ra, axis=1)
@@ -195,10 +201,15 @@ def blocksize_sweep(torch, n_big: int, cpu_check: bool):
     out = []
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    for n in (1, 64, 4096, 65536, n_big):
-        n = min(n, n_big)
-        il = np.arange(n_big, dtype=np.int32) if n == n_big else \
-            rng.choice(n_big, n, replace=False).astype(np.int32)
+    central = np.argsort(np.linalg.norm(x, axis=1))[:64].astype(np.int32)
+    for n in (1, 64, "central64", 4096, 65536, n_big):
+        label = n
+        if n == "central64":
+            il, n = central, 64
+        else:
+            n = min(n, n_big)
+            il = np.arange(n_big, dtype=np.int32) if n == n_big else \
+                rng.choice(n_big, n, replace=False).astype(np.int32)
         ilt = torch.as_tensor(il, device=g.dev)
         reps = 3 if n < n_big else 1
         with torch.cuda.stream(g.stream):
@@ -210,7 +221,9 @@ def blocksize_sweep(torch, n_big: int, cpu_check: bool):
         torch.cuda.synchronize()
         ms = ev0.elapsed_time(ev1) / reps
         rate = float(n) * n_big / (ms * 1e-3)
-        rec = {"n_active": n, "ms": ms, "interactions_per_s": rate,
+        rec = {"n_active": n, "i_list": "the 64 most central" if label == "central64" else
+               ("all" if n == n_big else "random (seed 1006)"),
+               "ms": ms, "interactions_per_s": rate,
                "frac_fp32_peak": FLOPS_PER_INTERACTION * rate / PEAK_FP32,
                "jbuffer_GBps": 40.0 * n_big / (ms * 1e-3) / 1e9}
         if cpu_check and n <= 4096:
@@ -222,7 +235,7 @@ def blocksize_sweep(torch, n_big: int, cpu_check: bool):
                                             np.linalg.norm(ra, axis=1)).max())
             rec["checked_particles"] = k
         out.append(rec)
-        log(f"N={n_big} n={n}: {ms:.3f} ms {rate:.3e} int/s")
+        log(f"N={n_big} n={label}: {ms:.3f} ms {rate:.3e} int/s")
     g.close()
     return {"workload": f"plummer_N{n_big}_eps1/4096_mixed_force_only", "points": out}
 
@@ -327,12 +340,13 @@ def ensemble_bench(torch, n_clusters: int, t_short: float, t_full: float, per_cl
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=N_DEFAULT, help="particles (default 196608)")
     ap.add_argument("--fp64-steps", type=int, default=1, help="timed FP64 steps (0 = skip)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=25.0,
+                    help="CPU oracle budget; all N particles are checked when it suffices")
     ap.add_argument("--no-energy", action="store_true")
     ap.add_argument("--blocksizes", type=int, default=0,
                     help="also measure force-only rates per block size at this N (e.g. 1048576)")
@@ -454,6 +468,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": total_ms / args.steps,
+        "ms_per_step_min": min(mixed.step_ms),
+        "ms_per_step_median": float(statistics.median(mixed.step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -465,7 +481,9 @@ def main():
                    "interactions_per_step": total_inter / args.steps,
                    "block_steps_per_step": mixed.block_steps,
                    "autotuned_shapes": mixed.tuning},
-        "full_sweep": {"ms": sweep_ms, "interactions_per_s": sweep_rate,
+        "full_sweep": {"ms": sweep_ms, "ms_min": min(mixed.sweep_ms),
+                       "ms_median": float(statistics.median(mixed.sweep_ms)),
+                       "interactions_per_s": sweep_rate,
                        "returns": "acc, jerk, potential (FP64, 56 B per particle)",
                        "ms_acc_jerk_only": sweep_nopot_ms,
                        "interactions_per_s_acc_jerk_only":
