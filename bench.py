@@ -337,6 +337,140 @@ def ensemble_bench(torch, n_clusters: int, t_short: float, t_full: float, per_cl
     return res
 
 
+def perfmodel_bench(torch, n_list, t_end: float):
+    """The single-PC performance model of section 4.1 recast for one GPU.
+
+    The paper models one N-body time unit as a sum over block steps of
+    tau_pred*N + tau_force*n*N + tau_corr*n and fixes n at its average
+    0.20*N^0.81.  On the GPU each block step also has a fixed cost t0 (kernel
+    launches and their latency) and tau_force depends on n.  For every N this
+    measures the run to t_end (wall time, steps, updates, the sequence of block
+    sizes), tau_pred, tau_force(n) for n = 4^k, and tau_corr, then predicts the
+    run time two ways: the paper's form with the measured average block size,
+    and summed over the recorded block sizes.  t0 is fitted on the smallest N."""
+    import numpy as np
+
+    from nbody_inputs import plummer
+    from paper_0709_4552_amd import NBODY_PREC_MIXED, NBody
+    eps = 1.0 / 256
+    kw = dict(eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(g, fn, reps):
+        with torch.cuda.stream(g.stream):
+            fn()
+            ev0.record(g.stream)
+            for _ in range(reps):
+                fn()
+            ev1.record(g.stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) * 1e-3 / reps
+
+    rows = []
+    for idx, n_tot in enumerate(n_list):
+        x, v, m = plummer(n_tot, 1100 + idx)
+        g = NBody(x, v, m, eps, **kw)
+        g.init()
+        for n_probe in (n_tot, 1024, 128, 16, 1):
+            g.autotune(min(n_probe, n_tot))
+        fields = (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)
+        snap = [t.clone() for t in fields]
+
+        def restore():
+            for d, s_ in zip(fields, snap):
+                d.copy_(s_)
+            torch.cuda.synchronize()
+
+        g.run_until(1.0 / 64)  # builds the step graph outside the timed run
+        restore()
+        s0 = g.stats()
+        t0 = time.perf_counter()
+        g.run_until(t_end)
+        torch.cuda.synchronize()
+        t_app = time.perf_counter() - t0
+        s1 = g.stats()
+        steps = s1["block_steps"] - s0["block_steps"]
+        updates = s1["updates"] - s0["updates"]
+        inter = s1["interactions"] - s0["interactions"]
+        # the block sizes of the same run, step by step (same steps: same state)
+        restore()
+        sizes = []
+        while True:
+            t, n = g.step_block(True)
+            sizes.append(n)
+            if t >= t_end:
+                break
+        sizes = np.asarray(sizes, dtype=np.int64)
+        # tau_pred: the predictor pass over all N
+        restore()
+        tau_pred = timed(g, lambda: g.predict(0.0), 20) / n_tot
+        # tau_force(n) at n = 4^k and at n = N
+        rng = np.random.Generator(np.random.PCG64(1006))
+        grid_n = sorted(set([4 ** k for k in range(0, 20) if 4 ** k < n_tot] + [n_tot]))
+        tau_f = {}
+        for n in grid_n:
+            il = torch.as_tensor(rng.choice(n_tot, n, replace=False).astype(np.int32), device=g.dev)
+            reps = max(1, min(50, int(2e10 / (n * n_tot))))
+            tau_f[n] = timed(g, lambda: g.force_jerk(il, 0.0, want_pot=False), reps) / (n * n_tot)
+        g.close()
+        # tau_corr: every particle due at once in a shared-step copy of the system
+        gs = NBody(x, v, m, eps, eta=0.01, eta_init=0.01, dt_min_log2=-8, dt_max_log2=-8,
+                   precision=NBODY_PREC_MIXED)
+        gs.init()
+        everyone = torch.arange(n_tot, dtype=torch.int32, device=gs.dev)
+        gs.predict(2.0 ** -8)
+        acc, jerk, _ = gs.force_jerk(everyone, 2.0 ** -8, want_pot=False)
+        sfields = (gs.pos, gs.vel, gs.acc, gs.jerk, gs.t_tick, gs.level)
+        ssnap = [t.clone() for t in sfields]
+        corr = []
+        for _ in range(3):
+            for d, s_ in zip(sfields, ssnap):
+                d.copy_(s_)
+            torch.cuda.synchronize()
+            with torch.cuda.stream(gs.stream):
+                ev0.record(gs.stream)
+                gs.correct(everyone, 2.0 ** -8, acc, jerk)
+                ev1.record(gs.stream)
+            torch.cuda.synchronize()
+            corr.append(ev0.elapsed_time(ev1) * 1e-3)
+        gs.sync()
+        gs.close()
+        tau_corr = min(corr) / n_tot
+        ln = np.log(np.array(grid_n, dtype=np.float64))
+        lt = np.log(np.array([tau_f[n] for n in grid_n]))
+
+        def tau_force(n):
+            return float(np.exp(np.interp(np.log(np.maximum(n, 1)), ln, lt)))
+
+        n_mean = updates / max(steps, 1)
+        rows.append({"N": n_tot, "t_end": t_end, "T_app_s": t_app, "block_steps": int(steps),
+                     "updates": int(updates), "interactions": inter, "n_mean": n_mean,
+                     "n_paper_0.20N^0.81": 0.20 * n_tot ** 0.81,
+                     "tau_pred_us": tau_pred * 1e6, "tau_corr_us": tau_corr * 1e6,
+                     "tau_force_us": {str(n): tau_f[n] * 1e6 for n in grid_n},
+                     "_force_sum_s": float(sum(tau_force(n) * n * n_tot for n in sizes)),
+                     "_force_mean_s": tau_force(n_mean) * inter,
+                     "_rest_s": steps * (tau_pred * n_tot) + updates * tau_corr})
+        log(f"perfmodel N={n_tot}: T_app {t_app:.3f} s, {steps} steps, n_mean {n_mean:.1f} "
+            f"(0.20 N^0.81 = {0.20 * n_tot ** 0.81:.1f}), tau_pred {tau_pred * 1e9:.2f} ns, "
+            f"tau_corr {tau_corr * 1e9:.2f} ns")
+    # fixed cost per block step, from the smallest N (force work negligible there)
+    r0 = rows[0]
+    t_fixed = (r0["T_app_s"] - r0["_force_sum_s"] - r0["_rest_s"]) / r0["block_steps"]
+    for r in rows:
+        r["t0_us"] = t_fixed * 1e6
+        r["T_model_per_step_sizes_s"] = r["block_steps"] * t_fixed + r["_force_sum_s"] + r["_rest_s"]
+        r["T_model_mean_block_s"] = r["block_steps"] * t_fixed + r["_force_mean_s"] + r["_rest_s"]
+        r["model_over_measured"] = r["T_model_per_step_sizes_s"] / r["T_app_s"]
+        for k in ("_force_sum_s", "_force_mean_s", "_rest_s"):
+            r[k.lstrip("_")] = r.pop(k)
+        log(f"perfmodel N={r['N']}: T_app {r['T_app_s']:.3f} s, model (block sizes) "
+            f"{r['T_model_per_step_sizes_s']:.3f} s, model (mean block) {r['T_model_mean_block_s']:.3f} s")
+    return {"workload": f"plummer_eps1/256_mixed_to_t{t_end}", "t0_fitted_on_N": r0["N"],
+            "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -355,6 +489,10 @@ def main():
     ap.add_argument("--ensemble-t", type=float, default=1.0 / 64)
     ap.add_argument("--ensemble-full", type=float, default=0.0)
     ap.add_argument("--no-per-cluster", action="store_true")
+    ap.add_argument("--perfmodel", type=str, default="",
+                    help="also fit and check the per-step performance model on these N "
+                         "(comma separated, e.g. 1024,4096,16384,65536,196608)")
+    ap.add_argument("--perfmodel-t", type=float, default=1.0)
     ap.add_argument("--sweep-only", type=int, default=0,
                     help="only time this many full sweeps, then one 512 MiB elementwise "
                          "copy of known size (for hardware-counter runs); prints one JSON line")
@@ -460,6 +598,9 @@ def main():
     extra_ens = ensemble_bench(torch, args.ensemble, args.ensemble_t, args.ensemble_full,
                                not args.no_per_cluster) if args.ensemble else None
 
+    extra_pm = perfmodel_bench(torch, [int(q) for q in args.perfmodel.split(",")],
+                               args.perfmodel_t) if args.perfmodel else None
+
     line = {
         "metric": METRIC,
         "value": value,
@@ -501,6 +642,7 @@ def main():
         "energy": energy,
         "block_sizes": extra_bs,
         "ensemble": extra_ens,
+        "perfmodel": extra_pm,
         "context": {"grape6af_interactions_per_s": 1.0 / 4.3e-10,
                     "grape6af_simultaneous_interactions": 42},
     }
