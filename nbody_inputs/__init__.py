@@ -5,3 +5,4 @@ correction or time-step arithmetic, so that the oracle and the HIP path stay
 independent of each other while reading identical inputs.
 """
 from .plummer import plummer, ensemble_sizes, ensemble  # noqa: F401
+from .imf import salpeter_masses, plummer_salpeter  # noqa: F401

@@ -25,10 +25,15 @@
 // are flushed to FP64 accumulators every 128 j.  The jerk is kept as two sums,
 // sum m s^{-3/2} w and sum m s^{-5/2} (r.w) r, combined in FP64 as the first
 // minus three times the second (one multiply less per interaction).
-// Near field: a pair with m_max/s > near_frac*|a_i| (|a_i| from the
-// particle's stored acceleration) can carry a term comparable to the whole
-// force, where FP32 rounding would exceed the error budget; such pairs are
-// masked out of the FP32 sums and evaluated in FP64 in a rarely taken branch.
+// Near field: a pair whose term can exceed near_frac*|a_i| (|a_i| from the
+// particle's stored acceleration) can be comparable to the whole force, where
+// FP32 rounding would exceed the error budget; such pairs are masked out of
+// the FP32 sums, recorded, and evaluated in FP64 after the tile.  With equal
+// masses the test is m_max/s > near_frac*|a_i| (one compare per pair); with a
+// mass spectrum (PM) it is m_j/s > near_frac*|a_i|, one multiply more, since
+// m_max would flag nearly every pair.  A lane records at most kNearCap pairs
+// per tile; masking stops while a whole group of pairs still fits, so every
+// masked pair is recorded and none is lost.
 // FP64: every operation in double precision; s^{-1/2} from the hardware
 // estimate refined by one third-order Newton step.
 //
@@ -71,8 +76,9 @@ struct ForceOcc {
     static constexpr int kMinBlocks = (MIXED && I == 1 && LJ == 1) ? 5 : 1;
 };
 
-template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL>
+template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL, bool PM>
 __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_force(ForceArgs fa) {
+    static_assert(MIXED || !PM, "per-pair near test only in the mixed form");
     static_assert(LJ == 1 || LJ == 4 || LJ == 16 || LJ == 64 || LJ == 256, "J_LANES");
     static_assert(LJ == 1 || I == 1, "several i per lane only without lane groups");
     constexpr int NI = kWG / LJ;  // i-slots per workgroup
@@ -199,12 +205,13 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                 xh[ii] = p.x; yh[ii] = p.y; zh[ii] = p.z; mi[ii] = p.w;
                 xl[ii] = q.x; yl[ii] = q.y; zl[ii] = q.z; vxi[ii] = q.w;
                 vyi[ii] = r.x; vzi[ii] = r.y;
-                // near-field threshold on s from |a_i| (0 = none)
+                // near-field threshold on s from |a_i| (0 = none): per unit of
+                // m_j with PM, else for m_max
                 float sc = 0.f;
                 if (fa.near_frac > 0.f) {
                     const double ha = sqrt(fa.hax[i] * fa.hax[i] + fa.hay[i] * fa.hay[i] +
                                            fa.haz[i] * fa.haz[i]);
-                    const double v = (double)fa.mmax[c] / ((double)fa.near_frac * ha);
+                    const double v = (PM ? 1.0 : (double)fa.mmax[c]) / ((double)fa.near_frac * ha);
                     sc = (ha > 0.0 && v < 3.0e38) ? (float)v : 0.f;
                 }
                 scrit[ii] = sc;
@@ -305,7 +312,7 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                                 const float wz = r[g].y - vzi[ii];
                                 const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, fa.eps2f)));
                                 const float rw = __builtin_fmaf(dz, wz, __builtin_fmaf(dy, wy, dx * wx));
-                                const bool near = s < sc_eff[ii];
+                                const bool near = s < (PM ? p[g].w * sc_eff[ii] : sc_eff[ii]);
                                 nr[g][ii] = near;
                                 any = any || near;
                                 float rinv = __builtin_amdgcn_rsqf(s);
@@ -331,8 +338,9 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                             }
                         }
                         if (__ballot(any) != 0ull) {
-                            // rare: remember the pairs for the FP64 pass after the tile;
-                            // a full list stops masking for the rest of the tile
+                            // rare: remember the pairs for the FP64 pass after the tile.
+                            // Masking stops once fewer than G slots are free, so the
+                            // pairs of one group always fit: every masked pair is kept.
 #pragma unroll
                             for (int g = 0; g < G; g++) {
 #pragma unroll
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                                     if (nr[g][ii] && ncnt[ii] < kNearCap) {
                                         const int t = lj + (ch * CHJ + u + g) * LJ;
                                         sNear[(ii * kNearCap + ncnt[ii]) * kWG + tid] = (uint16_t)t;
-                                        if (++ncnt[ii] == kNearCap)
+                                        if (++ncnt[ii] > kNearCap - G)
                                             sc_eff[ii] = 0.f;
                                     }
                                 }
@@ -374,7 +382,15 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                     for (int k = 0; k < ncnt[ii]; k++) {
                         const int t = sNear[(ii * kNearCap + k) * kWG + tid];
                         const int64_t j = tb + t;
-                        if (j == gi[ii] || j >= j1)
+                        if (j == gi[ii]) {
+                            // the self pair was masked: put back the FP32 self term the
+                            // writer removes, so it is removed exactly once whichever
+                            // lane of the group met it
+                            if (POT && !EXCL)
+                                acc[ii].p += (double)(mi[ii] * __builtin_amdgcn_rsqf(fa.eps2f));
+                            continue;
+                        }
+                        if (j >= j1)
                             continue;
                         const float4 p = jP(tb, j1, t);
                         const float4 q = jQ(tb, j1, t);
@@ -501,12 +517,12 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                 if (!valid[ii])
                     continue;
                 double pot = -acc[ii].p;
-                if (POT && !EXCL && js == 0) {
-                    // remove the self term m_i eps^{-1}, evaluated as in the loop
-                    // (in the mixed form only if the FP32 loop did not mask it)
+                if (POT && !EXCL && gi[ii] >= j0 && gi[ii] < j1) {
+                    // remove the self term m_i eps^{-1}, evaluated as in the loop, in
+                    // the item whose j-slice holds i (mixed: if the FP32 loop masked
+                    // it, the near-field pass has put the same value back)
                     if (MIXED) {
-                        if (!(fa.eps2f < scrit[ii]))
-                            pot += (double)(mi[ii] * __builtin_amdgcn_rsqf(fa.eps2f));
+                        pot += (double)(mi[ii] * __builtin_amdgcn_rsqf(fa.eps2f));
                     } else {
                         pot += M[ii] * rsqrt_f64(fa.eps2);
                     }
@@ -548,36 +564,40 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
 using KernelFn = void (*)(ForceArgs);
 
 template <int I, int LJ, int JT>
-KernelFn pick(int mixed, int pot, int excl) {
-    const int key = mixed * 4 + pot * 2 + excl;
+KernelFn pick(int mixed, int pot, int excl, int pm) {
+    const int key = mixed ? 4 + (pm ? 4 : 0) + pot * 2 + excl : pot * 2 + excl;
     switch (key) {
-        case 0: return k_force<I, LJ, JT, false, false, false>;
-        case 1: return k_force<I, LJ, JT, false, false, true>;
-        case 2: return k_force<I, LJ, JT, false, true, false>;
-        case 3: return k_force<I, LJ, JT, false, true, true>;
-        case 4: return k_force<I, LJ, JT, true, false, false>;
-        case 5: return k_force<I, LJ, JT, true, false, true>;
-        case 6: return k_force<I, LJ, JT, true, true, false>;
-        default: return k_force<I, LJ, JT, true, true, true>;
+        case 0: return k_force<I, LJ, JT, false, false, false, false>;
+        case 1: return k_force<I, LJ, JT, false, false, true, false>;
+        case 2: return k_force<I, LJ, JT, false, true, false, false>;
+        case 3: return k_force<I, LJ, JT, false, true, true, false>;
+        case 4: return k_force<I, LJ, JT, true, false, false, false>;
+        case 5: return k_force<I, LJ, JT, true, false, true, false>;
+        case 6: return k_force<I, LJ, JT, true, true, false, false>;
+        case 7: return k_force<I, LJ, JT, true, true, true, false>;
+        case 8: return k_force<I, LJ, JT, true, false, false, true>;
+        case 9: return k_force<I, LJ, JT, true, false, true, true>;
+        case 10: return k_force<I, LJ, JT, true, true, false, true>;
+        default: return k_force<I, LJ, JT, true, true, true, true>;
     }
 }
 
-KernelFn lookup(const Shape &sh, int mixed, int pot, int excl) {
+KernelFn lookup(const Shape &sh, int mixed, int pot, int excl, int pm) {
     if (sh.j_tile != 256)
         return nullptr;
-    if (sh.j_lanes == 1 && sh.i_per_lane == 1) return pick<1, 1, 256>(mixed, pot, excl);
-    if (sh.j_lanes == 1 && sh.i_per_lane == 2) return pick<2, 1, 256>(mixed, pot, excl);
+    if (sh.j_lanes == 1 && sh.i_per_lane == 1) return pick<1, 1, 256>(mixed, pot, excl, pm);
+    if (sh.j_lanes == 1 && sh.i_per_lane == 2) return pick<2, 1, 256>(mixed, pot, excl, pm);
     if (sh.i_per_lane != 1) return nullptr;
-    if (sh.j_lanes == 4) return pick<1, 4, 256>(mixed, pot, excl);
-    if (sh.j_lanes == 16) return pick<1, 16, 256>(mixed, pot, excl);
-    if (sh.j_lanes == 64) return pick<1, 64, 256>(mixed, pot, excl);
-    if (sh.j_lanes == 256) return pick<1, 256, 256>(mixed, pot, excl);
+    if (sh.j_lanes == 4) return pick<1, 4, 256>(mixed, pot, excl, pm);
+    if (sh.j_lanes == 16) return pick<1, 16, 256>(mixed, pot, excl, pm);
+    if (sh.j_lanes == 64) return pick<1, 64, 256>(mixed, pot, excl, pm);
+    if (sh.j_lanes == 256) return pick<1, 256, 256>(mixed, pot, excl, pm);
     return nullptr;
 }
 
 }  // namespace
 
-bool force_shape_supported(const Shape &sh) { return lookup(sh, 1, 0, 0) != nullptr; }
+bool force_shape_supported(const Shape &sh) { return lookup(sh, 1, 0, 0, 0) != nullptr; }
 
 int force_j_step(const Shape &sh) {
     // must match JTX of k_force
@@ -586,8 +606,8 @@ int force_j_step(const Shape &sh) {
     return sh.j_tile;
 }
 
-int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self) {
-    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self);
+int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self, int pair_mass) {
+    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self, pair_mass);
     if (!fn)
         return 0;
     int blocks = 0;
@@ -597,9 +617,9 @@ int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self) 
     return blocks;
 }
 
-hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self,
+hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self, int pair_mass,
                         const ForceArgs &fa, int grid, hipStream_t s) {
-    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self);
+    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self, pair_mass);
     if (!fn)
         return hipErrorInvalidValue;
     ForceArgs a = fa;

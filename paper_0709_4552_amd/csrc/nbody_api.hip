@@ -57,6 +57,7 @@ struct nbody_ctx {
     int cls_grid[kClasses];  // 0 = derive from occupancy
     int32_t cls_min_n[kClasses];
     int occ_cache[kClasses][2][2];  // occupancy per class, want_pot, exclude_self (0 = unknown)
+    int pair_mass = 0;  // mixed form: some cluster's masses differ, near test per pair
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -111,7 +112,7 @@ int grid_of(nbody_ctx *c, int cls, int want_pot, int excl) {
     int &occ = c->occ_cache[cls][want_pot ? 1 : 0][excl ? 1 : 0];
     if (occ <= 0)
         occ = std::max(1, force_occupancy(c->cls_shape[cls], c->pr.precision == NBODY_PREC_MIXED,
-                                          want_pot, excl));
+                                          want_pot, excl, c->pair_mass));
     return occ * c->n_cu;
 }
 
@@ -191,7 +192,7 @@ hipError_t launch_classes(nbody_ctx *c, ForceArgs fa, int mixed, int want_pot, i
         }
         done |= mask;
         fa.cls_mask = mask;
-        hipError_t e = launch_force(sh, mixed, want_pot, excl, fa, grid, c->stream);
+        hipError_t e = launch_force(sh, mixed, want_pot, excl, c->pair_mass, fa, grid, c->stream);
         if (e != hipSuccess)
             return e;
     }
@@ -273,15 +274,28 @@ hipError_t enqueue_block_step(nbody_ctx *c) {
                                  c->ctl, c->stream);
 }
 
+void drop_graph(nbody_ctx *c);
+
 // Largest |mass| of each cluster (the near-field threshold of the mixed form
-// uses it), from a host copy of the masses.
+// uses it), and whether any cluster has unequal masses (then the mixed form
+// tests every pair with its own m_j), from a host copy of the masses.
 hipError_t upload_mass_max(nbody_ctx *c, const double *mh) {
     std::vector<float> mx(c->pr.C, 0.f);
+    bool unequal = false;
     for (int k = 0; k < c->pr.C; k++) {
         double v = 0.0;
-        for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++)
+        const double m0 = mh[c->off_h[k]];
+        for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++) {
             v = std::max(v, std::fabs(mh[i]));
+            unequal = unequal || mh[i] != m0;
+        }
         mx[k] = (float)v;
+    }
+    const int pm = (c->pr.precision == NBODY_PREC_MIXED && unequal) ? 1 : 0;
+    if (pm != c->pair_mass) {
+        c->pair_mass = pm;
+        std::memset(c->occ_cache, 0, sizeof(c->occ_cache));
+        drop_graph(c);
     }
     return hipMemcpy(c->mmax_d, mx.data(), mx.size() * sizeof(float), hipMemcpyHostToDevice);
 }

@@ -212,9 +212,11 @@ hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, 
 
 // ---- force (kernels_force.hip) --------------------------------------------
 bool force_shape_supported(const Shape &sh);
-int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self);
+// pair_mass (mixed form only): near-field test per pair with m_j instead of
+// the cluster's largest mass; for clusters whose masses are not all equal
+int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self, int pair_mass);
 int force_j_step(const Shape &sh);
-hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self,
+hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self, int pair_mass,
                         const ForceArgs &fa, int grid, hipStream_t s);
 
 }  // namespace nb

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from nbody_inputs import ensemble, plummer
+from nbody_inputs import ensemble, plummer, plummer_salpeter
 from paper_0709_4552_amd import NBODY_PREC_FP64, NBODY_PREC_MIXED, NBody, NBodyError
 from paper_0709_4552_amd import _lib
 
@@ -110,6 +110,116 @@ def test_force_jerk_matches_oracle(prec, n):
     assert relerr(acc, ra).max() <= TOL[prec]["a"]
     assert relerr(jerk, rj).max() <= TOL[prec]["j"]
     assert relerr(pot, rp).max() <= TOL[prec]["p"]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_force_jerk_unequal_masses(prec):
+    # Salpeter masses over 0.1-100: the near field of the mixed form is sized
+    # by the cluster's largest mass, the case that stresses it most
+    note(f"force_jerk salpeter prec={prec}")
+    N = 3000
+    x, v, m = plummer_salpeter(N, 1013)
+    eps = 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    t = 3 * 2.0 ** -12
+    g.predict(t)
+    il = np.arange(N, dtype=np.int32)
+    acc, jerk, pot = g.force_jerk(il, t)
+    xg, vg, ag, jg, tg, _ = g.host_state()
+    xp, vp = oracle.predict(t, tg, xg, vg, ag, jg)
+    ra, rj, rp = oracle.force(xp, vp, m, eps, il)
+    ea = relerr(acc.T.cpu().numpy(), ra)
+    ej = relerr(jerk.T.cpu().numpy(), rj)
+    note(f"  max rel acc err {ea.max():.2e} (heaviest star {ea[np.argmax(m)]:.2e}), "
+         f"jerk {ej.max():.2e}")
+    assert ea.max() <= TOL[prec]["a"]
+    # the mixed form carries velocities in FP32: jerk to a few 1e-5 (the bar
+    # is on the acceleration)
+    assert ej.max() <= (5e-5 if prec == NBODY_PREC_MIXED else TOL[prec]["j"])
+    assert relerr(pot.cpu().numpy(), rp).max() <= TOL[prec]["p"]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_near_field_overflow_keeps_every_pair(prec):
+    # 40 particles within 1e-6 of one point, eps = 1e-4: for each of them all
+    # 39 others are near-field pairs, far more than one lane records per tile.
+    # Every pair must still be counted once (FP64 when recorded, FP32 after
+    # the list is full) and the potential's self term removed exactly once.
+    note(f"near-field overflow prec={prec}")
+    N = 2000
+    x, v, m = plummer(N, 1016)
+    x = x.copy()
+    rng = np.random.Generator(np.random.PCG64(1016))
+    x[500:540] = x[500] + 1e-6 * rng.standard_normal((40, 3))
+    eps = 1e-4
+    g = NBody(x, v, m, eps, dt_min_log2=-30, dt_max_log2=-3, precision=prec)
+    g.init()
+    t = 2.0 ** -30
+    g.predict(t)
+    il = np.arange(N, dtype=np.int32)
+    acc, jerk, pot = g.force_jerk(il, t)
+    xg, vg, ag, jg, tg, _ = g.host_state()
+    xp, vp = oracle.predict(t, tg, xg, vg, ag, jg)
+    ra, rj, rp = oracle.force(xp, vp, m, eps, il)
+    ea = relerr(acc.T.cpu().numpy(), ra)
+    ej = relerr(jerk.T.cpu().numpy(), rj)
+    ep = relerr(pot.cpu().numpy(), rp)
+    note(f"  max rel acc err {ea.max():.2e} (clump {ea[500:540].max():.2e}), jerk {ej.max():.2e}, "
+         f"pot {ep.max():.2e}")
+    # pairs 1e-6 apart: one ulp of a predicted position (GPU and oracle
+    # predictors round differently) moves r by 1e-10 relative, so FP64 is
+    # held to 1e-9 here
+    a_tol = 1e-9 if prec == NBODY_PREC_FP64 else TOL[prec]["a"]
+    assert ea.max() <= a_tol
+    assert ej.max() <= max(TOL[prec]["j"], 1e-8)
+    assert ep.max() <= TOL[prec]["p"]
+    g.close()
+
+
+def test_unequal_masses_full_size_sweep_mixed():
+    # N = 16384 Salpeter cluster, the start-up sweep on every particle
+    note("salpeter N=16384 sweep")
+    N = 16384
+    x, v, m = plummer_salpeter(N, 1014)
+    eps = 1 / 1024
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g.init()
+    il = np.arange(N, dtype=np.int32)
+    g.predict(0.0)
+    acc, _, _ = g.force_jerk(il, 0.0, want_pot=False)
+    ra, _, _ = oracle.force(x, v, m, eps, il)
+    ea = relerr(acc.T.cpu().numpy(), ra)
+    note(f"  max rel acc err {ea.max():.2e}, p99.9 {np.quantile(ea, 0.999):.2e}")
+    assert ea.max() <= 1e-6
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_unequal_masses_block_steps_energy(prec):
+    # block steps with a wide mass spectrum: energy error within the bar and
+    # close to the FP64 oracle's own integration error
+    note(f"salpeter block steps prec={prec}")
+    N = 2048
+    x, v, m = plummer_salpeter(N, 1015)
+    eps, t_end = 1 / 256, 0.25
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    g.run_until(t_end)
+    xg, vg, _, _, tg, _ = g.host_state()
+    assert np.all(tg == t_end)
+    E0 = sum(oracle.energy(x, v, m, eps))
+    dE = abs(sum(oracle.energy(xg, vg, m, eps)) - E0) / abs(E0)
+    ref = oracle.System(x, v, m, oracle.params(eps, eta=0.01, eta_init=0.01, dt_min_log2=-20,
+                                               dt_max_log2=-3))
+    ref.run(t_end)
+    dE_ref = abs(sum(ref.energy()) - E0) / abs(E0)
+    note(f"  |dE/E| gpu {dE:.2e} oracle {dE_ref:.2e} stats={g.stats()}")
+    assert dE <= 1e-5
+    if prec == NBODY_PREC_FP64:  # the mixed form adds its own rounding drift
+        assert dE <= max(10 * dE_ref, 1e-8)
     g.close()
 
 

@@ -44,3 +44,37 @@ def test_ensemble_sizes_and_offsets():
     for k in range(8):
         nk = offs[k + 1] - offs[k]
         assert np.all(m[offs[k]:offs[k + 1]] == 1.0 / nk)
+
+
+def test_salpeter_masses_follow_the_power_law():
+    # against the analytic distribution dN/dm ~ m^-2.35 on [0.1, 100]
+    from nbody_inputs import salpeter_masses
+    n, lo, hi, a = 200000, 0.1, 100.0, 2.35
+    m = salpeter_masses(n, 77)
+    assert m.min() >= lo and m.max() <= hi
+    assert np.array_equal(m, salpeter_masses(n, 77))
+    e = 1.0 - a
+    ms = np.sort(m)
+    cdf = (ms ** e - lo ** e) / (hi ** e - lo ** e)
+    emp_hi = np.arange(1, n + 1) / n
+    d = max(np.max(emp_hi - cdf), np.max(cdf - (emp_hi - 1.0 / n)))
+    assert d < 1.63 / np.sqrt(n)  # Kolmogorov-Smirnov, 1% level
+    z = (hi ** e - lo ** e) / e  # normalisation of m^-a
+    mean = (hi ** (2 - a) - lo ** (2 - a)) / (2 - a) / z
+    var = (hi ** (3 - a) - lo ** (3 - a)) / (3 - a) / z - mean ** 2
+    assert abs(m.mean() - mean) < 5.0 * np.sqrt(var / n)
+    # about 0.35 solar masses on average for this range
+    assert 0.3 < mean < 0.4
+
+
+def test_plummer_salpeter_units_and_centre():
+    from nbody_inputs import plummer, plummer_salpeter
+    x, v, m = plummer_salpeter(5000, 31)
+    x0, v0, _ = plummer(5000, 31)
+    assert abs(m.sum() - 1.0) < 1e-12
+    assert np.abs((m[:, None] * x).sum(axis=0)).max() < 1e-14
+    assert np.abs((m[:, None] * v).sum(axis=0)).max() < 1e-14
+    # the same positions and velocities, only shifted as a whole
+    dx = x - x0
+    assert np.abs(dx - dx[0]).max() < 1e-12
+    assert m.max() / m.min() > 100.0

@@ -93,6 +93,22 @@ def test_equilateral_triangle_points_to_centroid():
                                    rtol=1e-14, atol=1e-15)
 
 
+def test_momentum_balance_with_unequal_masses():
+    # Salpeter masses spanning a factor 1000: the force on i must weigh the
+    # sources by m_j, or sum m_i a_i no longer vanishes
+    from nbody_inputs import plummer_salpeter
+    x, v, m = plummer_salpeter(400, 8)
+    a, j, p = oracle.force(x, v, m, 1 / 64)
+    assert np.all(np.abs((m[:, None] * a).sum(0)) < 1e-14 * np.abs(m[:, None] * a).sum())
+    assert np.all(np.abs((m[:, None] * j).sum(0)) < 1e-14 * np.abs(m[:, None] * j).sum())
+    # potential energy counted from both ends agrees: sum_i m_i phi_i = 2 U
+    u = 0.0
+    for i in range(len(m)):
+        r = np.sqrt(((x[i + 1:] - x[i]) ** 2).sum(1) + (1 / 64) ** 2)
+        u -= (m[i] * m[i + 1:] / r).sum()
+    assert (m * p).sum() == pytest.approx(2 * u, rel=1e-13)
+
+
 def test_momentum_and_angular_momentum_rates_vanish():
     x, v, m = plummer(512, 7)
     a, j, _ = oracle.force(x, v, m, 1 / 64)
