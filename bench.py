@@ -337,6 +337,69 @@ def ensemble_bench(torch, n_clusters: int, t_short: float, t_full: float, per_cl
     return res
 
 
+def salpeter_bench(torch, n: int, t_end: float, cpu_check: bool):
+    """Unequal masses: a Plummer sphere with Salpeter masses (0.1-100, seed
+    1017), eps = 1/1024, mixed form (its per-pair near-field variant): the full
+    sweep rate, its accuracy on a sample (the most massive, the most central and
+    random particles), and block steps to t_end."""
+    import numpy as np
+
+    from nbody_inputs import plummer_salpeter
+    from paper_0709_4552_amd import NBODY_PREC_MIXED, NBody
+    x, v, m = plummer_salpeter(n, 1017)
+    eps = 1.0 / 1024
+    g = NBody(x, v, m, eps, eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3,
+              precision=NBODY_PREC_MIXED)
+    g.init()
+    for n_probe in (n, 1024, 128, 16, 1):
+        g.autotune(min(n_probe, n))
+    fields = (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)
+    snap = [t.clone() for t in fields]
+    g.predict(0.0)
+    il = torch.arange(n, dtype=torch.int32, device=g.dev)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    with torch.cuda.stream(g.stream):
+        g.force_jerk(il, 0.0, want_pot=False)
+        ev0.record(g.stream)
+        for _ in range(3):
+            acc, _, _ = g.force_jerk(il, 0.0, want_pot=False)
+        ev1.record(g.stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / 3
+    out = {"workload": f"plummer_salpeter0.1-100_N{n}_eps1/1024_mixed", "n": n,
+           "mass_ratio_max_min": float(m.max() / m.min()),
+           "sweep_ms_acc_jerk": ms, "sweep_interactions_per_s": float(n) * n / (ms * 1e-3)}
+    if cpu_check:
+        import oracle
+        rng = np.random.Generator(np.random.PCG64(1018))
+        r = np.linalg.norm(x, axis=1)
+        sample = np.unique(np.concatenate([np.argsort(-m)[:256], np.argsort(r)[:256],
+                                           rng.integers(0, n, 3584)]))
+        ra, _, _ = oracle.force(x, v, m, eps, sample)
+        a = acc.T.cpu().numpy()[sample]
+        e = np.linalg.norm(a - ra, axis=1) / np.linalg.norm(ra, axis=1)
+        out.update({"max_rel_acc_err": float(e.max()), "median_rel_acc_err": float(np.median(e)),
+                    "checked_particles": int(sample.size),
+                    "checked": "the 256 most massive, the 256 most central, random"})
+    for d, s_ in zip(fields, snap):
+        d.copy_(s_)
+    torch.cuda.synchronize()
+    s0 = g.stats()
+    t0 = time.perf_counter()
+    g.run_until(t_end)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    s1 = g.stats()
+    inter = s1["interactions"] - s0["interactions"]
+    out.update({"t_end": t_end, "block_steps": s1["block_steps"] - s0["block_steps"],
+                "steps_s": wall, "steps_interactions_per_s": inter / wall})
+    log(f"salpeter N={n}: sweep {ms:.2f} ms, to t={t_end}: {wall:.3f} s "
+        f"({inter / wall:.3e} int/s), max err {out.get('max_rel_acc_err', float('nan')):.2e}")
+    g.close()
+    return out
+
+
 def perfmodel_bench(torch, n_list, t_end: float):
     """The single-PC performance model of section 4.1 recast for one GPU.
 
@@ -493,6 +556,8 @@ def main():
                     help="also fit and check the per-step performance model on these N "
                          "(comma separated, e.g. 1024,4096,16384,65536,196608)")
     ap.add_argument("--perfmodel-t", type=float, default=1.0)
+    ap.add_argument("--salpeter", type=int, default=0,
+                    help="also run a Salpeter-mass Plummer sphere of this N (e.g. 196608)")
     ap.add_argument("--sweep-only", type=int, default=0,
                     help="only time this many full sweeps, then one 512 MiB elementwise "
                          "copy of known size (for hardware-counter runs); prints one JSON line")
@@ -598,6 +663,8 @@ def main():
     extra_ens = ensemble_bench(torch, args.ensemble, args.ensemble_t, args.ensemble_full,
                                not args.no_per_cluster) if args.ensemble else None
 
+    extra_sal = salpeter_bench(torch, args.salpeter, 1.0 / 16, not args.no_cpu_baseline) \
+        if args.salpeter else None
     extra_pm = perfmodel_bench(torch, [int(q) for q in args.perfmodel.split(",")],
                                args.perfmodel_t) if args.perfmodel else None
 
@@ -643,6 +710,7 @@ def main():
         "block_sizes": extra_bs,
         "ensemble": extra_ens,
         "perfmodel": extra_pm,
+        "salpeter": extra_sal,
         "context": {"grape6af_interactions_per_s": 1.0 / 4.3e-10,
                     "grape6af_simultaneous_interactions": 42},
     }
