@@ -307,7 +307,7 @@ __device__ int64_t block_exclusive_scan(int64_t v, int64_t *tmp, int64_t *total)
 __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t *off, PlanDev pl,
                                                        int32_t *n_act, int64_t *t_next,
                                                        DevCtl *ctl, int64_t part_cap,
-                                                       ClassTable ct, int32_t j_tile,
+                                                       ClassTable ct,
                                                        int32_t host_n, int64_t host_t,
                                                        int32_t count_stats) {
     __shared__ int64_t tmp[kPlanThreads];
@@ -378,7 +378,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
         }
     const int64_t ib_size = ct.ib[cls];
     const int64_t grid_res = ct.grid[cls];
-    j_tile = ct.jt[cls];
+    const int32_t j_tile = ct.jt[cls];
     // one cluster: choose S by the cost model (every thread tries one S)
     if (C == 1) {
         const int64_t n = pl.n_cur[0];
@@ -486,45 +486,44 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
     }
 }
 
-// One cluster: the same plan computed by a single wave without barriers.
-// Lane l evaluates j-split counts S = l+1, l+65, ... (up to kMaxSlices) with
-// the cost model above; a wave minimum picks the best (ties -> smaller S).
-__global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, PlanDev pl,
-                                                 int32_t *n_act, int64_t *t_next, DevCtl *ctl,
-                                                 int64_t part_cap, ClassTable ct, int32_t j_tile,
-                                                 int32_t host_n, int64_t host_t,
-                                                 int32_t count_stats) {
+// One cluster, one wave (lane L looks at level L): the next block's time and
+// size from the level counts; n = 0 (and the time unchanged) when the next
+// time lies beyond t_end.  Every lane returns the same values.
+__device__ inline void next_block_wave(const Params &pr, const PlanDev &pl, int64_t t_end,
+                                       int64_t *T_out, int64_t *n_out) {
     static_assert(kLevels == 64, "one level per lane");
-    const int lane = threadIdx.x;
-    int64_t n;
-    int64_t tcur;
-    if (host_n >= 0) {
-        n = host_n;
-        tcur = host_t;
-    } else if (host_n == kPlanFromLists) {
-        n = uniform_i32(n_act[0]);
-        tcur = uniform_i64(t_next[0]);
-    } else {
-        // lane L looks at level L
-        const bool in = lane >= pr.lev_min && lane <= pr.lev_max;
-        const int32_t cnt = in ? pl.lev_cnt[lane] : 0;
-        const int sh = in ? pr.lev_max - lane : 0;
-        const int64_t tnow = uniform_i64(pl.t_now[0]);
-        int64_t T = cnt > 0 ? level_next(tnow, sh) : INT64_MAX;
-        for (int o = 32; o > 0; o >>= 1) {
-            const int64_t other = __shfl_xor(T, o);
-            T = other < T ? other : T;
-        }
-        int32_t due = (cnt > 0 && T != INT64_MAX && (T & (((int64_t)1 << sh) - 1)) == 0) ? cnt : 0;
-        for (int o = 32; o > 0; o >>= 1)
-            due += __shfl_xor(due, o);
-        n = uniform_i32(due);
-        tcur = uniform_i64(T);
-        if (tcur == INT64_MAX || tcur > uniform_i64(ctl->t_end_tick)) {
-            n = 0;
-            tcur = tnow;
-        }
+    const int lane = threadIdx.x & 63;
+    const bool in = lane >= pr.lev_min && lane <= pr.lev_max;
+    const int32_t cnt = in ? pl.lev_cnt[lane] : 0;
+    const int sh = in ? pr.lev_max - lane : 0;
+    const int64_t tnow = uniform_i64(pl.t_now[0]);
+    int64_t T = cnt > 0 ? level_next(tnow, sh) : INT64_MAX;
+    for (int o = 32; o > 0; o >>= 1) {
+        const int64_t other = __shfl_xor(T, o);
+        T = other < T ? other : T;
     }
+    int32_t due = (cnt > 0 && T != INT64_MAX && (T & (((int64_t)1 << sh) - 1)) == 0) ? cnt : 0;
+    for (int o = 32; o > 0; o >>= 1)
+        due += __shfl_xor(due, o);
+    int64_t n = uniform_i32(due);
+    T = uniform_i64(T);
+    if (T == INT64_MAX || T > t_end) {
+        n = 0;
+        T = tnow;
+    }
+    *T_out = T;
+    *n_out = n;
+}
+
+// One cluster, one wave: the plan of an evaluation of n particles at time
+// tcur.  Lane l evaluates j-split counts S = l+1, l+65, ... (up to kMaxSlices)
+// with the cost model above; a wave minimum picks the best (ties -> smaller
+// S); lane 0 writes the plan.  No barriers and no early exit, so it can run
+// inside a larger kernel.
+__device__ inline void plan_single_wave(const int64_t *off, const PlanDev &pl, DevCtl *ctl,
+                                        int64_t part_cap, const ClassTable &ct, int64_t n,
+                                        int64_t tcur, int32_t count_stats) {
+    const int lane = threadIdx.x & 63;
     const int64_t Nc = off[1] - off[0];
     int cls = kClasses - 1;
     for (int k = 0; k < kClasses; k++)
@@ -534,7 +533,7 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
         }
     const int64_t ib_size = ct.ib[cls];
     const int64_t grid_res = ct.grid[cls];
-    j_tile = ct.jt[cls];
+    const int64_t j_tile = ct.jt[cls];
     const int64_t tiles = (Nc + j_tile - 1) / j_tile;
     const int64_t nib = (n + ib_size - 1) / ib_size;
     const int64_t grid = plan_grid(grid_res, nib, tiles);
@@ -552,44 +551,106 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
         const int64_t other = __shfl_xor(key, o);
         key = other < key ? other : key;
     }
-    if (lane != 0)
-        return;
-    int64_t S = key == INT64_MAX ? 1 : (key & 2047) + 1;
-    int64_t items = 0, parts = 0;
-    int32_t jl = 0, Sfin = 0;
-    if (n > 0 && Nc > 0) {
-        const int64_t tiles_per = (tiles + S - 1) / S;
-        jl = (int32_t)(tiles_per * j_tile);
-        Sfin = (int32_t)((Nc + jl - 1) / jl);
-        items = nib * Sfin;
-        parts = Sfin > 1 ? (int64_t)Sfin * n : 0;
+    if (lane == 0) {
+        const int64_t S = key == INT64_MAX ? 1 : (key & 2047) + 1;
+        int64_t items = 0, parts = 0;
+        int32_t jl = 0, Sfin = 0;
+        if (n > 0 && Nc > 0) {
+            const int64_t tiles_per = (tiles + S - 1) / S;
+            jl = (int32_t)(tiles_per * j_tile);
+            Sfin = (int32_t)((Nc + jl - 1) / jl);
+            items = nib * Sfin;
+            parts = Sfin > 1 ? (int64_t)Sfin * n : 0;
+        }
+        pl.n_cur[0] = (int32_t)n;
+        pl.t_cur[0] = tcur;
+        pl.S[0] = Sfin;
+        pl.jlen[0] = jl;
+        pl.item_begin[0] = 0;
+        pl.item_begin[1] = items;
+        pl.part_begin[0] = 0;
+        ctl->total_items = items;
+        ctl->part_used = parts;
+        ctl->item_counter = 0;
+        ctl->cls = cls;
+        ctl->s_max = Sfin > 1 ? Sfin : 0;
+        ctl->n_last = (int32_t)n;
+        ctl->any_active = n > 0;
+        if (count_stats) {
+            ctl->steps += n > 0 ? 1ull : 0ull;
+            ctl->updates += (unsigned long long)n;
+            ctl->interactions += (double)n * (double)Nc;
+        }
     }
-    if (host_n == kPlanFromLists) {
+}
+
+// One cluster, an explicit evaluation: n and t from the host, or from n_act /
+// t_next (set by the host, reset here).
+__global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, PlanDev pl,
+                                                 int32_t *n_act, int64_t *t_next, DevCtl *ctl,
+                                                 int64_t part_cap, ClassTable ct,
+                                                 int32_t host_n, int64_t host_t,
+                                                 int32_t count_stats) {
+    int64_t n = host_n, tcur = host_t;
+    if (host_n < 0) {
+        n = uniform_i32(n_act[0]);
+        tcur = uniform_i64(t_next[0]);
+    }
+    plan_single_wave(off, pl, ctl, part_cap, ct, n, tcur, count_stats);
+    if (host_n < 0 && threadIdx.x == 0) {
         n_act[0] = 0;
         t_next[0] = LLONG_MAX;
-    } else if (host_n == kPlanFromLevels) {
-        n_act[0] = 0;  // compaction cursor
-        pl.t_now[0] = tcur;
     }
-    pl.n_cur[0] = (int32_t)n;
-    pl.t_cur[0] = tcur;
-    pl.S[0] = Sfin;
-    pl.jlen[0] = jl;
-    pl.item_begin[0] = 0;
-    pl.item_begin[1] = items;
-    pl.part_begin[0] = 0;
-    ctl->total_items = items;
-    ctl->part_used = parts;
-    ctl->item_counter = 0;
-    ctl->cls = cls;
-    ctl->s_max = Sfin > 1 ? Sfin : 0;
-    ctl->n_last = (int32_t)n;
-    ctl->any_active = n > 0;
-    if (count_stats) {
-        ctl->steps += n > 0 ? 1ull : 0ull;
-        ctl->updates += (unsigned long long)n;
-        ctl->interactions += (double)n * (double)Nc;
+}
+
+// One cluster, one block step's first kernel: every wave finds the next block
+// from the level counts (so no workgroup waits for another), workgroup 0 also
+// writes the plan, and every workgroup predicts its 256 particles to the block
+// time and appends the due ones to the active list.  The compaction cursor
+// starts at zero (reset by the previous step's corrector or by priming), and
+// the cluster's time advances in the corrector, after every workgroup here has
+// read it.
+template <int MIXED>
+__global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params pr, JBuf jb,
+                                                              const int64_t *off, PlanDev pl,
+                                                              int32_t *cursor, int32_t *i_list,
+                                                              DevCtl *ctl, int64_t part_cap,
+                                                              ClassTable ct) {
+    static_assert(kChunk == kWG, "one particle per thread");
+    __shared__ int32_t wcount[kWG / 64];
+    __shared__ int32_t base_s;
+    int64_t T, n;
+    next_block_wave(pr, pl, uniform_i64(ctl->t_end_tick), &T, &n);
+    if (blockIdx.x == 0 && threadIdx.x < 64)
+        plan_single_wave(off, pl, ctl, part_cap, ct, n, T, 1);
+    if (n == 0)  // the same in every wave: they all read the same counts
+        return;
+    const int64_t N = pr.n_total;
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    bool due = false;
+    if (i < N) {
+        const int64_t tk = st.tick[i];
+        due = tk + dt_ticks(pr.lev_max, st.lev[i]) == T;
+        predict_one<MIXED>(st, pr, jb, i, tk, T);
     }
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const unsigned long long bal = __ballot(due);
+    const int before = __popcll(bal & ((1ull << lane) - 1ull));
+    if (lane == 0)
+        wcount[w] = __popcll(bal);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int tot = 0;
+        for (int q = 0; q < kWG / 64; q++) {
+            const int cnt = wcount[q];
+            wcount[q] = tot;
+            tot += cnt;
+        }
+        base_s = tot ? atomicAdd(&cursor[0], tot) : 0;
+    }
+    __syncthreads();
+    if (due)
+        i_list[base_s + wcount[w] + before] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------- corrector
@@ -718,8 +779,9 @@ struct CorrArgs {
     State st;
     Params pr;
     const int64_t *t_cur;
+    int64_t *t_now;
     int32_t *lev_cnt;
-    const int32_t *cursor;  // compaction count of the step (checked against the plan)
+    int32_t *cursor;  // compaction count of the step (checked against the plan)
     DevCtl *ctl;
 };
 
@@ -898,8 +960,16 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
             atomicOr(&ca.ctl->err, err);
         if (clamps)
             atomicAdd(&ca.ctl->clamps, clamps);
-        if (fa.C == 1 && blockIdx.x == 0 && threadIdx.x == 0 && ca.cursor[0] != fa.n_cur[0])
-            atomicOr(&ca.ctl->err, kErrPlan);
+        if (fa.C == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
+            // one cluster: check the compaction against the plan, then close the
+            // step (cursor back to zero, the cluster's time advances)
+            const int32_t n = fa.n_cur[0];
+            if (ca.cursor[0] != n)
+                atomicOr(&ca.ctl->err, kErrPlan);
+            ca.cursor[0] = 0;
+            if (n > 0)
+                ca.t_now[0] = ca.t_cur[0];
+        }
     }
 }
 
@@ -992,10 +1062,11 @@ hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, 
 
 hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
-                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, DevCtl *ctl,
-                        hipStream_t s) {
+                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, int32_t *cursor,
+                        DevCtl *ctl, hipStream_t s) {
     hipError_t e;
     if ((e = launch_fill_i32(pl.lev_cnt, 0, (int64_t)pr.C * kLevels, s)) != hipSuccess ||
+        (e = launch_fill_i32(cursor, 0, pr.C, s)) != hipSuccess ||
         (e = launch_fill_i64(t_min, LLONG_MAX, pr.C, s)) != hipSuccess ||
         (e = launch_fill_i64(t_max, 0, pr.C, s)) != hipSuccess)
         return e;
@@ -1023,14 +1094,33 @@ hipError_t launch_predict_compact(const State &st, const Params &pr, const JBuf 
 
 hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, int32_t *n_act,
                        int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
-                       int32_t j_tile, int32_t host_n, int64_t host_t, int32_t count_stats,
-                       hipStream_t s) {
-    if (pr.C == 1)
+                       int32_t host_n, int64_t host_t, int32_t count_stats, hipStream_t s) {
+    if (pr.C == 1) {
+        // a single cluster's block steps plan inside k_plan_predict_compact
+        if (host_n == kPlanFromLevels)
+            return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_plan_one, dim3(1), dim3(64), 0, s, pr, off, pl, n_act, t_next, ctl,
-                           part_cap, ct, j_tile, host_n, host_t, count_stats);
-    else
+                           part_cap, ct, host_n, host_t, count_stats);
+    } else {
         hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, s, pr, off, pl, n_act, t_next,
-                           ctl, part_cap, ct, j_tile, host_n, host_t, count_stats);
+                           ctl, part_cap, ct, host_n, host_t, count_stats);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_plan_predict_compact(const State &st, const Params &pr, const JBuf &jb,
+                                       const int64_t *off, const PlanDev &pl, int32_t *cursor,
+                                       int32_t *i_list, DevCtl *ctl, int64_t part_cap,
+                                       const ClassTable &ct, hipStream_t s) {
+    if (pr.C != 1)
+        return hipErrorInvalidValue;
+    const unsigned g = (unsigned)((pr.n_total + kWG - 1) / kWG);
+    if (pr.precision == NBODY_PREC_MIXED)
+        hipLaunchKernelGGL(k_plan_predict_compact<1>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off,
+                           pl, cursor, i_list, ctl, part_cap, ct);
+    else
+        hipLaunchKernelGGL(k_plan_predict_compact<0>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off,
+                           pl, cursor, i_list, ctl, part_cap, ct);
     return hipGetLastError();
 }
 
@@ -1043,14 +1133,14 @@ hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_s
 }
 
 hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Params &pr,
-                                 const int32_t *cid, const PlanDev &pl, const int32_t *cursor,
+                                 const int32_t *cid, const PlanDev &pl, int32_t *cursor,
                                  const int32_t *s_max, DevCtl *ctl, hipStream_t s) {
     // the grid is fixed when a step is captured: one thread per particle for
     // unsplit and narrow splits, grid-stride waves / workgroups for wider ones
     const int64_t n = pr.n_total;
     const int64_t g = std::min<int64_t>(4096, std::max<int64_t>((n + kWG - 1) / kWG,
                                                                 std::min<int64_t>(n, 1024)));
-    const CorrArgs ca{st, pr, pl.t_cur, pl.lev_cnt, cursor, ctl};
+    const CorrArgs ca{st, pr, pl.t_cur, pl.t_now, pl.lev_cnt, cursor, ctl};
     hipLaunchKernelGGL(k_reduce_t<true>, dim3((unsigned)g), dim3(kWG), 0, s, fa, cid, n, s_max,
                        ca);
     return hipGetLastError();

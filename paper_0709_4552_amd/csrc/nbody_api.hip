@@ -213,7 +213,7 @@ hipError_t enqueue_force(nbody_ctx *c, const int32_t *i_list, int slots_at_offse
     if (host_n >= 0)
         only = class_of(c, host_n);
     hipError_t e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl,
-                               c->part_cap, ct, kJTile, host_n, host_t, count_stats, c->stream);
+                               c->part_cap, ct, host_n, host_t, count_stats, c->stream);
     if (e != hipSuccess)
         return e;
     ForceArgs fa = force_args(c, i_list, slots_at_offsets, acc, jerk, pot, stride);
@@ -247,23 +247,29 @@ int consume_error(nbody_ctx *c, const DevCtl &h) {
 // (which the caller owns and the explicit entry points may have changed).
 hipError_t enqueue_prime(nbody_ctx *c) {
     return launch_prime(c->st, c->pr, c->off_d, c->chunk_c_d, c->chunk_b_d, c->n_chunks, c->pl,
-                        c->t_next_d, c->t_max_d, c->ctl, c->stream);
+                        c->t_next_d, c->t_max_d, c->n_act_d, c->ctl, c->stream);
 }
 
 // One block step of every active cluster (section 4.1): plan the next block
-// from the level counts, predict and compact, force, then reduce the j-split
-// and correct in one pass.  Nothing here reads back to the host, so a batch
-// of steps is captured into one graph.
+// from the level counts, predict and compact (one kernel for a single
+// cluster, two for an ensemble), force, then reduce the j-split and correct in
+// one pass.  Nothing here reads back to the host, so a batch of steps is
+// captured into one graph.
 hipError_t enqueue_block_step(nbody_ctx *c) {
     const int excl = c->pr.eps2 == 0.0;
     const int mixed = c->pr.precision == NBODY_PREC_MIXED;
     const ClassTable ct = class_table(c, 0, excl);
-    hipError_t e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl,
-                               c->part_cap, ct, kJTile, kPlanFromLevels, 0, 1, c->stream);
-    if (e != hipSuccess)
-        return e;
-    e = launch_predict_compact(c->st, c->pr, c->jb, c->off_d, c->chunk_c_d, c->chunk_b_d,
-                               c->n_chunks, c->pl, c->n_act_d, c->i_list_d, c->stream);
+    hipError_t e;
+    if (c->pr.C == 1) {
+        e = launch_plan_predict_compact(c->st, c->pr, c->jb, c->off_d, c->pl, c->n_act_d,
+                                        c->i_list_d, c->ctl, c->part_cap, ct, c->stream);
+    } else {
+        e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl, c->part_cap, ct,
+                        kPlanFromLevels, 0, 1, c->stream);
+        if (e == hipSuccess)
+            e = launch_predict_compact(c->st, c->pr, c->jb, c->off_d, c->chunk_c_d, c->chunk_b_d,
+                                       c->n_chunks, c->pl, c->n_act_d, c->i_list_d, c->stream);
+    }
     if (e != hipSuccess)
         return e;
     ForceArgs fa = force_args(c, c->i_list_d, 1, c->acc_new, c->jerk_new, nullptr, c->pr.n_total);

@@ -184,20 +184,23 @@ hipError_t launch_predict(const State &st, const Params &pr, const JBuf &jb, con
                           int use_host_t, hipStream_t s);
 hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
-                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, DevCtl *ctl,
-                        hipStream_t s);
+                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, int32_t *cursor,
+                        DevCtl *ctl, hipStream_t s);
 hipError_t launch_predict_compact(const State &st, const Params &pr, const JBuf &jb,
                                   const int64_t *off, const int32_t *chunk_c,
                                   const int64_t *chunk_b, int64_t n_chunks, const PlanDev &pl,
                                   int32_t *cursor, int32_t *i_list, hipStream_t s);
 hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, int32_t *n_act,
                        int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
-                       int32_t j_tile, int32_t host_n, int64_t host_t, int32_t count_stats,
-                       hipStream_t s);
+                       int32_t host_n, int64_t host_t, int32_t count_stats, hipStream_t s);
+hipError_t launch_plan_predict_compact(const State &st, const Params &pr, const JBuf &jb,
+                                       const int64_t *off, const PlanDev &pl, int32_t *cursor,
+                                       int32_t *i_list, DevCtl *ctl, int64_t part_cap,
+                                       const ClassTable &ct, hipStream_t s);
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
                          const int32_t *s_max, hipStream_t s);
 hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Params &pr,
-                                 const int32_t *cid, const PlanDev &pl, const int32_t *cursor,
+                                 const int32_t *cid, const PlanDev &pl, int32_t *cursor,
                                  const int32_t *s_max, DevCtl *ctl, hipStream_t s);
 hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_list,
                           int32_t slots_at_offsets, const int64_t *off, const int32_t *cid,
