@@ -345,6 +345,57 @@ def test_ensemble_matches_independent_oracles(prec):
     g.close()
 
 
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_tiny_clusters_and_ragged_sizes(prec):
+    # clusters of 1, 2, 3 and 5 particles beside ragged larger ones (sizes not
+    # multiples of 256): a lone particle moves in a straight line, the rest
+    # follow their own oracles
+    note(f"tiny clusters prec={prec}")
+    sizes = [1, 2, 3, 5, 257, 300]
+    parts = [plummer(n, 2000 + k) for k, n in enumerate(sizes)]
+    x = np.concatenate([q[0] for q in parts])
+    v = np.concatenate([q[1] for q in parts])
+    m = np.concatenate([q[2] for q in parts])
+    x[0] = (0.3, -0.2, 0.1)  # the lone particle: somewhere, moving
+    v[0] = (0.5, 0.25, -0.75)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    eps, T = 1 / 256, 1 / 16
+    prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-4)
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-4, precision=prec, cluster_offset=offs)
+    g.init()
+    g.run_until(T)
+    xg, vg, _, _, tg, _ = g.host_state()
+    assert np.all(tg == T)
+    np.testing.assert_allclose(xg[0], x[0] + T * v[0], rtol=0, atol=1e-15)
+    np.testing.assert_array_equal(vg[0], v[0])
+    for k in range(1, len(sizes)):
+        sl = slice(offs[k], offs[k + 1])
+        ref = oracle.System(x[sl], v[sl], m[sl], prm)
+        ref.run(T)
+        tol = 1e-10 if prec == NBODY_PREC_FP64 else 1e-6
+        assert np.abs(xg[sl] - ref.x).max() <= tol, k
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_unsoftened_unequal_masses(prec):
+    # eps = 0 (self pair skipped) together with a mass spectrum (per-pair near
+    # test in the mixed form)
+    note(f"eps=0 salpeter prec={prec}")
+    x, v, m = plummer_salpeter(400, 1019)
+    g = NBody(x, v, m, 0.0, dt_min_log2=-30, dt_max_log2=-3, precision=prec)
+    g.init()
+    il = np.arange(400, dtype=np.int32)
+    g.predict(0.0)
+    acc, jerk, pot = g.force_jerk(il, 0.0)
+    ra, rj, rp = oracle.force(x, v, m, 0.0, il)
+    assert relerr(acc.T.cpu().numpy(), ra).max() <= TOL[prec]["a"]
+    assert relerr(pot.cpu().numpy(), rp).max() <= TOL[prec]["p"]
+    ej = relerr(jerk.T.cpu().numpy(), rj).max()
+    assert ej <= (5e-5 if prec == NBODY_PREC_MIXED else TOL[prec]["j"])
+    g.close()
+
+
 def test_error_paths():
     note("error paths")
     x, v, m = plummer(500, 1007)
