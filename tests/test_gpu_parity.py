@@ -503,6 +503,34 @@ def test_runs_are_bitwise_deterministic():
 
 
 @pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_graph_replays_equal_eager_steps(prec):
+    # run_until replays a captured 32-step graph again and again, with host
+    # reads and synchronisations between the replays; step_block runs the
+    # same kernels eagerly, one step per call.  Every checkpoint must agree
+    # bit for bit.
+    note(f"graph vs eager prec={prec}")
+    x, v, m = plummer(3000, 1020)
+    kw = dict(dt_min_log2=-20, dt_max_log2=-4, precision=prec)
+    a = NBody(x, v, m, 1 / 256, **kw)
+    b = NBody(x, v, m, 1 / 256, **kw)
+    a.init()
+    b.init()
+    steps = 0
+    for t in (1 / 64, 1 / 32, 3 / 64, 1 / 16):
+        steps += a.run_until(t)
+        while True:
+            tb, _ = b.step_block()
+            if tb >= t:
+                break
+        for u, w in zip(a.host_state(), b.host_state()):
+            assert np.array_equal(u, w), t
+    assert steps > 3 * 32  # several graph replays
+    assert a.stats() == b.stats()
+    a.close()
+    b.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
 def test_autotune_keeps_results(prec):
     note(f"autotune prec={prec}")
     N = 2500
