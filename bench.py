@@ -171,9 +171,17 @@ def cpu_baseline(x, v, m, sweep_acc, budget_s: float):
     ra, rj, rp = oracle.force(x, v, m, EPS, sample)
     dt = time.perf_counter() - t0
     rate = sample.size * float(n) / dt
-    out = {"value": rate, "unit": "interactions/s", "cores": oracle.threads(), "kind": "oracle",
+    cores = oracle.threads()
+    # the same oracle on one thread, over the first 64 particles of the sample
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.force(x, v, m, EPS, sample[:64])
+    rate1 = 64.0 * n / (time.perf_counter() - t0)
+    oracle.set_threads(cores)
+    out = {"value": rate, "unit": "interactions/s", "cores": cores, "kind": "oracle",
            "sample": f"oracle acc+jerk+pot of {sample.size} particles ({what}) against all "
-                     f"N={n}, FP64, {dt:.1f} s"}
+                     f"N={n}, FP64, {dt:.1f} s",
+           "value_1_thread": rate1}
     errs = {}
     for name, (a, j) in sweep_acc.items():
         ea = np.linalg.norm(a[sample] - ra, axis=1) / np.linalg.norm(ra, axis=1)
