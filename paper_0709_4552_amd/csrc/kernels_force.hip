@@ -56,12 +56,28 @@ __device__ inline double rsqrt_f64(double s) {
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
+// One DPP lane move of a double (two 32-bit moves).  Rows that ROW_MASK leaves
+// out receive 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline double dpp_move(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Sum over each group of LJ consecutive lanes (LJ a power of two, <= 64) with
+// DPP moves only, no LDS permutes: quad swaps (lane ^ 1, lane ^ 2), then the
+// half-row and row mirrors (each pairs the two halves of an 8- and a 16-lane
+// span), then the row broadcasts of lanes 15 and 31.  The last lane of each
+// group (lane index LJ - 1 within it) ends with the group's sum; for LJ <= 16
+// every lane of the group does.  The order of the additions is fixed.
 template <int LJ>
 __device__ inline double group_sum(double v) {
-    // butterfly over the LJ consecutive lanes of a group (LJ <= 64)
-#pragma unroll
-    for (int o = LJ / 2; o > 0; o >>= 1)
-        v += __shfl_xor(v, o);
+    static_assert(LJ >= 1 && LJ <= 64 && (LJ & (LJ - 1)) == 0, "group of 1..64 lanes");
+    if (LJ >= 2) v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
+    if (LJ >= 4) v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
+    if (LJ >= 8) v += dpp_move<0x141>(v);       // row_half_mirror
+    if (LJ >= 16) v += dpp_move<0x140>(v);      // row_mirror
+    if (LJ >= 32) v += dpp_move<0x142, 0xA>(v); // rows 1, 3 += lane 15 of rows 0, 2
+    if (LJ >= 64) v += dpp_move<0x143, 0xC>(v); // rows 2, 3 += lane 31
     return v;
 }
 
@@ -478,7 +494,7 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
 
         // ---- reduce the lane group (J_LANES > 1)
         bool writer = true;
-        if (LJ > 1 && LJ <= 64) {
+        if constexpr (LJ > 1 && LJ <= 64) {
             acc[0].ax = group_sum<LJ>(acc[0].ax);
             acc[0].ay = group_sum<LJ>(acc[0].ay);
             acc[0].az = group_sum<LJ>(acc[0].az);
@@ -487,14 +503,14 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
             acc[0].jz = group_sum<LJ>(acc[0].jz);
             if (POT)
                 acc[0].p = group_sum<LJ>(acc[0].p);
-            writer = lj == 0;
-        } else if (LJ == 256) {
+            writer = lj == LJ - 1;
+        } else if constexpr (LJ == 256) {
             double v[7] = {acc[0].ax, acc[0].ay, acc[0].az, acc[0].jx, acc[0].jy, acc[0].jz, acc[0].p};
 #pragma unroll
             for (int q = 0; q < 7; q++)
                 v[q] = group_sum<64>(v[q]);
             __syncthreads();
-            if ((tid & 63) == 0) {
+            if ((tid & 63) == 63) {
 #pragma unroll
                 for (int q = 0; q < 7; q++)
                     sRed[(tid >> 6) * 7 + q] = v[q];
