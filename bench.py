@@ -43,6 +43,11 @@ SWEEP_TRAFFIC = {"force_source_sha256_prefix": "55fa12b57b1ae359", "read_bytes":
                  "write_bytes": 66.2e6}
 
 
+# Autotuner probe sizes, one per block-size class (n >= 2048, >= 256, >= 32,
+# >= 4, below), each inside the range of block sizes the class serves.
+CLASS_PROBES = (16384, 1024, 128, 16, 1)
+
+
 def sweep_traffic():
     import hashlib
     src = os.path.join(ROOT, "paper_0709_4552_amd", "csrc", "kernels_force.hip")
@@ -66,9 +71,10 @@ class Run:
                        precision=precision)
         self.g.init()
         g = self.g
-        # autotune every block-size class (outside any timed region)
+        # autotune every block-size class (outside any timed region), each at a
+        # block size in the middle of the range it serves in block steps
         self.tuning = []
-        for n_probe in sorted({g.n, min(g.n, 1024), min(g.n, 128), min(g.n, 16), 1}, reverse=True):
+        for n_probe in sorted({min(g.n, p) for p in CLASS_PROBES}, reverse=True):
             t, ms = g.autotune(n_probe)
             t["n_probe"] = n_probe
             t["ms"] = ms
@@ -359,7 +365,7 @@ def salpeter_bench(torch, n: int, t_end: float, cpu_check: bool):
     g = NBody(x, v, m, eps, eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3,
               precision=NBODY_PREC_MIXED)
     g.init()
-    for n_probe in (n, 1024, 128, 16, 1):
+    for n_probe in CLASS_PROBES:
         g.autotune(min(n_probe, n))
     fields = (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)
     snap = [t.clone() for t in fields]
@@ -443,7 +449,7 @@ def perfmodel_bench(torch, n_list, t_end: float):
         x, v, m = plummer(n_tot, 1100 + idx)
         g = NBody(x, v, m, eps, **kw)
         g.init()
-        for n_probe in (n_tot, 1024, 128, 16, 1):
+        for n_probe in CLASS_PROBES:
             g.autotune(min(n_probe, n_tot))
         fields = (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)
         snap = [t.clone() for t in fields]

@@ -278,11 +278,13 @@ int nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *tuning);
  * Autotuner: for blocks of n_probe particles per cluster (1 <= n_probe; a
  * cluster smaller than n_probe uses all its particles), time one force
  * evaluation with every supported launch shape of the class that block size
- * falls in, and keep the fastest for that class.  Runs on the j-particle
- * buffer of the last prediction (valid after nbody_init) and writes only
- * the context's scratch buffers: the particle state is not changed.
- * Synchronises.  *best receives the chosen shape; *best_ms (may be NULL) the
- * best time of one force evaluation in milliseconds.
+ * falls in (best of four timed calls after one warm-up), and keep for that
+ * class the fastest; when the fastest is a lane-group shape, the widest lane
+ * group within 3% of it.
+ * Runs on the j-particle buffer of the last prediction (valid after
+ * nbody_init) and writes only the context's scratch buffers: the particle
+ * state is not changed.  Synchronises.  *best receives the chosen shape;
+ * *best_ms (may be NULL) its time for one force evaluation in milliseconds.
  */
 int nbody_autotune(nbody_ctx *ctx, int64_t n_probe, nbody_tuning *best, double *best_ms);
 

@@ -56,31 +56,6 @@ __device__ inline double rsqrt_f64(double s) {
     return fma(y * e, fma(0.375, e, 0.5), y);
 }
 
-// One DPP lane move of a double (two 32-bit moves).  Rows that ROW_MASK leaves
-// out receive 0.
-template <int CTRL, int ROW_MASK = 0xF>
-__device__ inline double dpp_move(double v) {
-    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, ROW_MASK, 0xF, false);
-}
-
-// Sum over each group of LJ consecutive lanes (LJ a power of two, <= 64) with
-// DPP moves only, no LDS permutes: quad swaps (lane ^ 1, lane ^ 2), then the
-// half-row and row mirrors (each pairs the two halves of an 8- and a 16-lane
-// span), then the row broadcasts of lanes 15 and 31.  The last lane of each
-// group (lane index LJ - 1 within it) ends with the group's sum; for LJ <= 16
-// every lane of the group does.  The order of the additions is fixed.
-template <int LJ>
-__device__ inline double group_sum(double v) {
-    static_assert(LJ >= 1 && LJ <= 64 && (LJ & (LJ - 1)) == 0, "group of 1..64 lanes");
-    if (LJ >= 2) v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
-    if (LJ >= 4) v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
-    if (LJ >= 8) v += dpp_move<0x141>(v);       // row_half_mirror
-    if (LJ >= 16) v += dpp_move<0x140>(v);      // row_mirror
-    if (LJ >= 32) v += dpp_move<0x142, 0xA>(v); // rows 1, 3 += lane 15 of rows 0, 2
-    if (LJ >= 64) v += dpp_move<0x143, 0xC>(v); // rows 2, 3 += lane 31
-    return v;
-}
-
 struct Acc64 {
     double ax, ay, az, jx, jy, jz, p;
 };
@@ -93,7 +68,7 @@ struct ForceOcc {
 };
 
 template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL, bool PM>
-__global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_force(ForceArgs fa) {
+__device__ __forceinline__ void force_body(const ForceArgs &fa) {
     static_assert(MIXED || !PM, "per-pair near test only in the mixed form");
     static_assert(LJ == 1 || LJ == 4 || LJ == 16 || LJ == 64 || LJ == 256, "J_LANES");
     static_assert(LJ == 1 || I == 1, "several i per lane only without lane groups");
@@ -353,7 +328,7 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
                                 f2z[ii] = __builtin_fmaf(be, dz, f2z[ii]);
                             }
                         }
-                        if (__ballot(any) != 0ull) {
+                        if (__builtin_expect(__ballot(any) != 0ull, 0)) {
                             // rare: remember the pairs for the FP64 pass after the tile.
                             // Masking stops once fewer than G slots are free, so the
                             // pairs of one group always fit: every masked pair is kept.
@@ -577,6 +552,30 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
     }
 }
 
+// One lane per i-particle (one or two per lane): a launch of its own.
+template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL, bool PM>
+__global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_force(ForceArgs fa) {
+    force_body<I, LJ, JT, MIXED, POT, EXCL, PM>(fa);
+}
+
+// Lane groups of 4, 16, 64 or 256 per i-particle: one launch serves every
+// class that uses any of them, with the group width of the class the plan
+// picked (log2 in fa.cls_lj), so a block step needs at most two force
+// launches whatever shapes the classes were tuned to.
+template <int JT, bool MIXED, bool POT, bool EXCL, bool PM>
+__global__ __launch_bounds__(kWG) void k_force_groups(ForceArgs fa) {
+    const int cls = uniform_i32(*fa.cls);
+    if (((fa.cls_mask >> cls) & 1) == 0)
+        return;
+    switch ((fa.cls_lj >> (4 * cls)) & 15u) {
+        case 2: force_body<1, 4, JT, MIXED, POT, EXCL, PM>(fa); break;
+        case 4: force_body<1, 16, JT, MIXED, POT, EXCL, PM>(fa); break;
+        case 6: force_body<1, 64, JT, MIXED, POT, EXCL, PM>(fa); break;
+        case 8: force_body<1, 256, JT, MIXED, POT, EXCL, PM>(fa); break;
+        default: atomicOr(fa.err, kErrPlan); break;
+    }
+}
+
 using KernelFn = void (*)(ForceArgs);
 
 template <int I, int LJ, int JT>
@@ -598,20 +597,40 @@ KernelFn pick(int mixed, int pot, int excl, int pm) {
     }
 }
 
+template <int JT>
+KernelFn pick_groups(int mixed, int pot, int excl, int pm) {
+    const int key = mixed ? 4 + (pm ? 4 : 0) + pot * 2 + excl : pot * 2 + excl;
+    switch (key) {
+        case 0: return k_force_groups<JT, false, false, false, false>;
+        case 1: return k_force_groups<JT, false, false, true, false>;
+        case 2: return k_force_groups<JT, false, true, false, false>;
+        case 3: return k_force_groups<JT, false, true, true, false>;
+        case 4: return k_force_groups<JT, true, false, false, false>;
+        case 5: return k_force_groups<JT, true, false, true, false>;
+        case 6: return k_force_groups<JT, true, true, false, false>;
+        case 7: return k_force_groups<JT, true, true, true, false>;
+        case 8: return k_force_groups<JT, true, false, false, true>;
+        case 9: return k_force_groups<JT, true, false, true, true>;
+        case 10: return k_force_groups<JT, true, true, false, true>;
+        default: return k_force_groups<JT, true, true, true, true>;
+    }
+}
+
 KernelFn lookup(const Shape &sh, int mixed, int pot, int excl, int pm) {
     if (sh.j_tile != 256)
         return nullptr;
     if (sh.j_lanes == 1 && sh.i_per_lane == 1) return pick<1, 1, 256>(mixed, pot, excl, pm);
     if (sh.j_lanes == 1 && sh.i_per_lane == 2) return pick<2, 1, 256>(mixed, pot, excl, pm);
-    if (sh.i_per_lane != 1) return nullptr;
-    if (sh.j_lanes == 4) return pick<1, 4, 256>(mixed, pot, excl, pm);
-    if (sh.j_lanes == 16) return pick<1, 16, 256>(mixed, pot, excl, pm);
-    if (sh.j_lanes == 64) return pick<1, 64, 256>(mixed, pot, excl, pm);
-    if (sh.j_lanes == 256) return pick<1, 256, 256>(mixed, pot, excl, pm);
+    if (force_shape_grouped(sh)) return pick_groups<256>(mixed, pot, excl, pm);
     return nullptr;
 }
 
 }  // namespace
+
+bool force_shape_grouped(const Shape &sh) {
+    return sh.i_per_lane == 1 && sh.j_tile == 256 &&
+           (sh.j_lanes == 4 || sh.j_lanes == 16 || sh.j_lanes == 64 || sh.j_lanes == 256);
+}
 
 bool force_shape_supported(const Shape &sh) { return lookup(sh, 1, 0, 0, 0) != nullptr; }
 

@@ -605,19 +605,23 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
 
 // One cluster, one block step's first kernel: every wave finds the next block
 // from the level counts (so no workgroup waits for another), workgroup 0 also
-// writes the plan, and every workgroup predicts its 256 particles to the block
-// time and appends the due ones to the active list.  The compaction cursor
-// starts at zero (reset by the previous step's corrector or by priming), and
-// the cluster's time advances in the corrector, after every workgroup here has
+// writes the plan, and every workgroup predicts its kPredictRounds * 256
+// particles to the block time (particle b + r*256 + thread in round r) and
+// appends the due ones to the active list, in (round, wave, lane) order after
+// one atomic on the cursor per workgroup.  The compaction cursor starts at
+// zero (reset by the previous step's corrector or by priming), and the
+// cluster's time advances in the corrector, after every workgroup here has
 // read it.
+constexpr int kPredictRounds = 4;
+
 template <int MIXED>
 __global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params pr, JBuf jb,
                                                               const int64_t *off, PlanDev pl,
                                                               int32_t *cursor, int32_t *i_list,
                                                               DevCtl *ctl, int64_t part_cap,
                                                               ClassTable ct) {
-    static_assert(kChunk == kWG, "one particle per thread");
-    __shared__ int32_t wcount[kWG / 64];
+    constexpr int R = kPredictRounds, W = kWG / 64;
+    __shared__ int32_t wcount[R * W];
     __shared__ int32_t base_s;
     int64_t T, n;
     next_block_wave(pr, pl, uniform_i64(ctl->t_end_tick), &T, &n);
@@ -626,22 +630,31 @@ __global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params p
     if (n == 0)  // the same in every wave: they all read the same counts
         return;
     const int64_t N = pr.n_total;
-    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    bool due = false;
-    if (i < N) {
-        const int64_t tk = st.tick[i];
-        due = tk + dt_ticks(pr.lev_max, st.lev[i]) == T;
-        predict_one<MIXED>(st, pr, jb, i, tk, T);
+    const int64_t b = (int64_t)blockIdx.x * (R * kWG) + threadIdx.x;
+    bool due[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int64_t i = b + r * kWG;
+        due[r] = false;
+        if (i < N) {
+            const int64_t tk = st.tick[i];
+            due[r] = tk + dt_ticks(pr.lev_max, st.lev[i]) == T;
+            predict_one<MIXED>(st, pr, jb, i, tk, T);
+        }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const unsigned long long bal = __ballot(due);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0)
-        wcount[w] = __popcll(bal);
+    int before[R];
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const unsigned long long bal = __ballot(due[r]);
+        before[r] = __popcll(bal & ((1ull << lane) - 1ull));
+        if (lane == 0)
+            wcount[r * W + w] = __popcll(bal);
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
         int tot = 0;
-        for (int q = 0; q < kWG / 64; q++) {
+        for (int q = 0; q < R * W; q++) {
             const int cnt = wcount[q];
             wcount[q] = tot;
             tot += cnt;
@@ -649,8 +662,10 @@ __global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params p
         base_s = tot ? atomicAdd(&cursor[0], tot) : 0;
     }
     __syncthreads();
-    if (due)
-        i_list[base_s + wcount[w] + before] = (int32_t)i;
+#pragma unroll
+    for (int r = 0; r < R; r++)
+        if (due[r])
+            i_list[base_s + wcount[r * W + w] + before[r]] = (int32_t)(b + r * kWG);
 }
 
 // ---------------------------------------------------------------- corrector
@@ -761,13 +776,16 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
 
 // ---------------------------------------------------------------- reduction
 // Sums the per-slice partial results of every slot whose cluster was split
-// into S > 1 j-slices.  Narrow splits (S <= 8): one thread per slot, slices in
-// order.  Wider: one workgroup per slot (thread t adds slices t, t+256, ...,
-// then a fixed tree) while there are no more slots than workgroups, else one
-// wave per slot (lane l adds slices l, l+64, ..., then a fixed butterfly), so
-// no workgroup walks through many slots behind barriers.  (Without the slot
-// count, for ensembles outside a block step, splits wider than 64 take a
-// workgroup.)  Every order is fixed, so results are bitwise reproducible for a
+// into S > 1 j-slices.  Slots are taken by groups of L lanes (L a power of two
+// up to 64, the same for the whole launch): lane l of a group adds slices l,
+// l+L, ... in order, a fixed DPP tree adds the group's lanes, and the group's
+// last lane stores the slot.  L is the smallest width that leaves each lane at
+// most four slices, widened (up to S) while the slots times L come to fewer
+// than kReduceLanes lanes, so that small blocks still spread over the chip;
+// loads of one slice are consecutive over the slots.  Splits wider than 64
+// with no more slots than workgroups take a workgroup per slot instead (thread
+// t adds slices t, t+256, ..., then DPP trees and the four wave sums in
+// order).  Every order is fixed, so results are bitwise reproducible for a
 // given plan.  With one cluster only the n live slots are visited.
 //
 // CORR (a block step): instead of storing a slot's sums, correct its particle
@@ -775,6 +793,8 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
 // kernel's direct output), and keep the per-level counts of the block-step
 // scheme current: level changes are gathered per workgroup in LDS (one
 // cluster) or added to the cluster's row directly (several).
+constexpr int64_t kReduceLanes = 1 << 17;
+
 struct CorrArgs {
     State st;
     Params pr;
@@ -789,7 +809,7 @@ template <bool CORR>
 __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *cid,
                                                   int64_t slot_space, const int32_t *s_max,
                                                   CorrArgs ca) {
-    __shared__ double red[7][kWG];
+    __shared__ double red[7][kWG / 64];
     __shared__ int32_t dlev[kLevels];
     const int smax = uniform_i32(*s_max);
     if (!CORR && smax <= 1)
@@ -847,35 +867,9 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
         n_tot = bound;
     else if (CORR)
         n_tot = uniform_i32(ca.ctl->n_last);
-    const bool wg_mode = n_tot >= 0 ? n_tot <= (int64_t)gridDim.x : smax > 64;
-    if (smax <= 8) {
-        for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < bound;
-             s += (int64_t)gridDim.x * blockDim.x) {
-            const int c = fa.C > 1 ? cid[s] : 0;
-            const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
-            const int64_t n = fa.n_cur[c];
-            const int S = fa.S[c];
-            if (k >= n || (!CORR && S <= 1))
-                continue;
-            double v[7];
-            if (S <= 1) {
-                direct(s, v);
-            } else {
-                const int64_t base = fa.part_begin[c] + k;
-#pragma unroll
-                for (int q = 0; q < 7; q++) {
-                    double sum = 0.0;
-                    for (int js = 0; js < S; js++)
-                        sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
-                    v[q] = sum;
-                }
-            }
-            emit(s, c, v);
-        }
-    } else if (wg_mode) {
-        // one workgroup per slot: thread t adds slices t, t+256, ...; then a
-        // fixed tree over the 256 threads
-        const int t = threadIdx.x;
+    const bool wg_mode = smax > 64 && (n_tot < 0 || n_tot <= (int64_t)gridDim.x);
+    if (wg_mode) {
+        const int t = threadIdx.x, lane = t & 63, w = t >> 6;
         for (int64_t s = blockIdx.x; s < bound; s += gridDim.x) {
             const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
             const int64_t k = fa.slots_at_offsets ? s - uniform_i64(fa.off[c]) : s;
@@ -892,64 +886,67 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                 continue;
             }
             const int64_t base = uniform_i64(fa.part_begin[c]) + k;
+            double v[7];
 #pragma unroll
             for (int q = 0; q < 7; q++) {
                 double sum = 0.0;
                 for (int js = t; js < S; js += kWG)
                     sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
-                red[q][t] = sum;
+                v[q] = group_sum<64>(sum);
             }
-            __syncthreads();
-            for (int o = kWG / 2; o > 0; o >>= 1) {
-                if (t < o) {
-#pragma unroll
-                    for (int q = 0; q < 7; q++)
-                        red[q][t] += red[q][t + o];
-                }
-                __syncthreads();
-            }
-            if (t == 0) {
-                double v[7];
+            if (lane == 63) {
 #pragma unroll
                 for (int q = 0; q < 7; q++)
-                    v[q] = red[q][0];
+                    red[q][w] = v[q];
+            }
+            __syncthreads();
+            if (t == 0) {
+#pragma unroll
+                for (int q = 0; q < 7; q++)
+                    v[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
                 emit(s, c, v);
             }
             __syncthreads();
         }
     } else {
-        const int lane = threadIdx.x & 63;
+        int L = 1;
+        while (L < 64 && L < smax && (4 * L < smax || (n_tot >= 0 && n_tot * L < kReduceLanes)))
+            L <<= 1;
+        const int lane = threadIdx.x & 63, l = lane & (L - 1);
+        const int64_t gpw = 64 / L;  // slot groups per wave
         const int64_t wave = (blockIdx.x * (int64_t)blockDim.x + threadIdx.x) >> 6;
         const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-        for (int64_t s = wave; s < bound; s += nwaves) {
-            const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
-            const int64_t k = fa.slots_at_offsets ? s - fa.off[c] : s;
-            const int64_t n = fa.n_cur[c];
-            const int S = fa.S[c];
-            if (k >= n)
-                continue;
-            if (S <= 1) {
-                if (CORR && lane == 0) {
-                    double v[7];
-                    direct(s, v);
-                    emit(s, c, v);
+        for (int64_t s0 = wave * gpw; s0 < bound; s0 += nwaves * gpw) {
+            const int64_t s = s0 + lane / L;
+            int c = 0, S = 0;
+            bool live = false;
+            int64_t k = 0, n = 0;
+            if (s < bound) {
+                c = fa.C > 1 ? cid[s] : 0;
+                k = fa.slots_at_offsets ? s - fa.off[c] : s;
+                n = fa.n_cur[c];
+                S = fa.S[c];
+                live = k < n && (CORR || S > 1);
+            }
+            double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (live && S > 1) {
+                const int64_t base = fa.part_begin[c] + k;
+                for (int js = l; js < S; js += L) {
+#pragma unroll
+                    for (int q = 0; q < 7; q++)
+                        v[q] += fa.part[q * fa.part_cap + base + (int64_t)js * n];
                 }
-                continue;
             }
-            const int64_t base = fa.part_begin[c] + k;
-            double v[7];
+            if (L > 1) {
 #pragma unroll
-            for (int q = 0; q < 7; q++) {
-                double sum = 0.0;
-                for (int js = lane; js < S; js += 64)
-                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
-#pragma unroll
-                for (int o = 32; o > 0; o >>= 1)
-                    sum += __shfl_xor(sum, o);
-                v[q] = sum;
+                for (int q = 0; q < 7; q++)
+                    v[q] = group_sum_rt(v[q], L);
             }
-            if (lane == 0)
+            if (live && l == L - 1) {
+                if (S <= 1)
+                    direct(s, v);
                 emit(s, c, v);
+            }
         }
     }
     if (CORR) {
@@ -1114,7 +1111,8 @@ hipError_t launch_plan_predict_compact(const State &st, const Params &pr, const 
                                        const ClassTable &ct, hipStream_t s) {
     if (pr.C != 1)
         return hipErrorInvalidValue;
-    const unsigned g = (unsigned)((pr.n_total + kWG - 1) / kWG);
+    const int64_t per_wg = (int64_t)kPredictRounds * kWG;
+    const unsigned g = (unsigned)((pr.n_total + per_wg - 1) / per_wg);
     if (pr.precision == NBODY_PREC_MIXED)
         hipLaunchKernelGGL(k_plan_predict_compact<1>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off,
                            pl, cursor, i_list, ctl, part_cap, ct);

@@ -171,23 +171,34 @@ ForceArgs force_args(nbody_ctx *c, const int32_t *i_list, int slots_at_offsets, 
     return fa;
 }
 
-// The force launches of a device-planned evaluation: one per distinct launch
-// shape and grid among the classes (or only class `only`); each runs only if
-// the plan picked one of the classes it serves.
+// The force launches of a device-planned evaluation (or only class `only`):
+// one per distinct launch among the classes, where classes share a launch if
+// their shapes are equal, or both lane-group shapes (one kernel serves those),
+// and their grids are equal; each launch runs only if the plan picked one of
+// the classes it serves.
 hipError_t launch_classes(nbody_ctx *c, ForceArgs fa, int mixed, int want_pot, int excl,
                           int only) {
+    fa.cls_lj = 0;
+    for (int k = 0; k < kClasses; k++) {
+        int lg = 0;
+        while ((1 << lg) < c->cls_shape[k].j_lanes)
+            lg++;
+        fa.cls_lj |= (uint32_t)lg << (4 * k);
+    }
     int done = 0;
     for (int k = 0; k < kClasses; k++) {
         if ((only >= 0 && k != only) || (done >> k) & 1)
             continue;
         const Shape &sh = c->cls_shape[k];
+        const bool grouped = force_shape_grouped(sh);
         const int grid = grid_of(c, k, want_pot, excl);
         int mask = 0;
         for (int q = k; q < kClasses; q++) {
             const Shape &o = c->cls_shape[q];
-            if ((only < 0 || q == only) && o.i_per_lane == sh.i_per_lane &&
-                o.j_lanes == sh.j_lanes && o.j_tile == sh.j_tile &&
-                grid_of(c, q, want_pot, excl) == grid)
+            const bool same = grouped ? force_shape_grouped(o)
+                                      : (o.i_per_lane == sh.i_per_lane &&
+                                         o.j_lanes == sh.j_lanes && o.j_tile == sh.j_tile);
+            if ((only < 0 || q == only) && same && grid_of(c, q, want_pot, excl) == grid)
                 mask |= 1 << q;
         }
         done |= mask;
@@ -855,15 +866,16 @@ int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *be
     hipEvent_t e0, e1;
     NB_TRY(hipEventCreate(&e0));
     NB_TRY(hipEventCreate(&e1));
-    double best_t = 1e300;
-    Shape best_s = keep;
+    // every candidate's time; the pick is made below
+    double cand_t[sizeof(cand) / sizeof(cand[0])];
     int rc = NBODY_OK;
+    int ci = 0;
     for (const Shape &sh : cand) {
         c->cls_shape[cls] = sh;
         c->cls_grid[cls] = 0;
         std::memset(c->occ_cache[cls], 0, sizeof(c->occ_cache[cls]));
         float ms_min = 1e30f;
-        for (int rep = 0; rep < 3 && rc == NBODY_OK; rep++) {
+        for (int rep = 0; rep < 5 && rc == NBODY_OK; rep++) {
             hipError_t e = hipSuccess;
             if (c->pr.C == 1) {
                 e = hipEventRecord(e0, c->stream);
@@ -897,9 +909,30 @@ int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *be
         }
         if (rc != NBODY_OK)
             break;
-        if (ms_min < best_t) {
-            best_t = ms_min;
-            best_s = sh;
+        cand_t[ci++] = ms_min;
+    }
+    // The fastest shape; if that is a lane-group shape, the widest lane group
+    // within 3% of it instead: the blocks a class meets in a run are spread
+    // around the probe size, and uneven over the clusters of an ensemble, and
+    // wider groups lose less on blocks smaller than the probe (all lane-group
+    // shapes share one launch, so the choice adds no launch to a step).
+    double best_t = 1e300;
+    Shape best_s = keep;
+    if (rc == NBODY_OK) {
+        int fq = 0;
+        for (int q = 1; q < ci; q++)
+            if (cand_t[q] < cand_t[fq])
+                fq = q;
+        best_t = cand_t[fq];
+        best_s = cand[fq];
+        if (force_shape_grouped(best_s)) {
+            const double lim = 1.03 * cand_t[fq];
+            for (int q = 0; q < ci; q++)
+                if (force_shape_grouped(cand[q]) && cand_t[q] <= lim &&
+                    cand[q].j_lanes > best_s.j_lanes) {
+                    best_t = cand_t[q];
+                    best_s = cand[q];
+                }
         }
     }
     (void)hipEventDestroy(e0);

@@ -154,6 +154,8 @@ struct ForceArgs {
     const double *m64;              // FP64 masses
     const float *mmax;              // [C] largest mass of each cluster
     float near_frac;                // 0 disables the near field
+    uint32_t cls_lj;                // lane-group launches: log2(j lanes) of class k
+                                    // in bits 4k..4k+3
 };
 
 struct Shape {
@@ -172,6 +174,43 @@ __device__ inline int64_t uniform_i64(int64_t v) {
     return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 __device__ inline int32_t uniform_i32(int32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// One DPP lane move of a double (two 32-bit moves).  Rows that ROW_MASK leaves
+// out receive 0.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline double dpp_move(double v) {
+    return __builtin_amdgcn_update_dpp(0.0, v, CTRL, ROW_MASK, 0xF, false);
+}
+
+// Sum over each group of L consecutive lanes (L a power of two, <= 64) with
+// DPP moves only, no LDS permutes: quad swaps (lane ^ 1, lane ^ 2), then the
+// half-row and row mirrors (each pairs the two halves of an 8- and a 16-lane
+// span), then the row broadcasts of lanes 15 and 31.  The last lane of each
+// group (lane index L - 1 within it) ends with the group's sum; for L <= 16
+// every lane of the group does.  The order of the additions is fixed.  Every
+// lane of the wave must take part.
+template <int L>
+__device__ inline double group_sum(double v) {
+    static_assert(L >= 1 && L <= 64 && (L & (L - 1)) == 0, "group of 1..64 lanes");
+    if (L >= 2) v += dpp_move<0xB1>(v);        // quad_perm [1,0,3,2]
+    if (L >= 4) v += dpp_move<0x4E>(v);        // quad_perm [2,3,0,1]
+    if (L >= 8) v += dpp_move<0x141>(v);       // row_half_mirror
+    if (L >= 16) v += dpp_move<0x140>(v);      // row_mirror
+    if (L >= 32) v += dpp_move<0x142, 0xA>(v); // rows 1, 3 += lane 15 of rows 0, 2
+    if (L >= 64) v += dpp_move<0x143, 0xC>(v); // rows 2, 3 += lane 31
+    return v;
+}
+
+// The same with a group width known only at run time (uniform over the wave).
+__device__ inline double group_sum_rt(double v, int L) {
+    if (L >= 2) v += dpp_move<0xB1>(v);
+    if (L >= 4) v += dpp_move<0x4E>(v);
+    if (L >= 8) v += dpp_move<0x141>(v);
+    if (L >= 16) v += dpp_move<0x140>(v);
+    if (L >= 32) v += dpp_move<0x142, 0xA>(v);
+    if (L >= 64) v += dpp_move<0x143, 0xC>(v);
+    return v;
+}
 
 // ---- launchers (kernels_step.hip) -----------------------------------------
 hipError_t launch_fill_i64(int64_t *p, int64_t v, int64_t n, hipStream_t s);
@@ -215,6 +254,10 @@ hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, 
 
 // ---- force (kernels_force.hip) --------------------------------------------
 bool force_shape_supported(const Shape &sh);
+// Lane-group shapes (one i per lane group of 4-256 lanes) share one kernel;
+// launch_force of such a shape needs fa.cls_lj filled for the classes in
+// fa.cls_mask.
+bool force_shape_grouped(const Shape &sh);
 // pair_mass (mixed form only): near-field test per pair with m_j instead of
 // the cluster's largest mass; for clusters whose masses are not all equal
 int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self, int pair_mass);

@@ -142,6 +142,51 @@ def test_force_jerk_unequal_masses(prec):
     g.close()
 
 
+SHAPES = [(1, 1), (2, 1), (1, 4), (1, 16), (1, 64), (1, 256)]
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+@pytest.mark.parametrize("kind", ["equal", "salpeter", "eps0"])
+def test_every_launch_shape_matches_oracle(prec, kind):
+    # every (i per lane, j lanes) shape of the force kernel, forced on every
+    # size class, over block sizes that give narrow and wide j-splits; equal
+    # masses, Salpeter masses (the per-pair near test) and eps = 0 (the self
+    # pair skipped); N = 2500 leaves a ragged last tile
+    note(f"every shape prec={prec} kind={kind}")
+    N = 2500
+    if kind == "salpeter":
+        x, v, m = plummer_salpeter(N, 1014)
+    else:
+        x, v, m = plummer(N, 1015)
+    eps = 0.0 if kind == "eps0" else 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    t = 7 * 2.0 ** -13
+    g.predict(t)
+    xg, vg, ag, jg, tg, _ = g.host_state()
+    xp, vp = oracle.predict(t, tg, xg, vg, ag, jg)
+    rng = np.random.Generator(np.random.PCG64(77))
+    cases = []
+    for n in (1, 5, 40, 300, N):
+        il = np.arange(N, dtype=np.int32) if n == N else rng.integers(0, N, n).astype(np.int32)
+        cases.append((il, oracle.force(xp, vp, m, eps, il)))
+    scale = 10.0 if kind == "eps0" else 1.0
+    jtol = 5e-5 if (kind == "salpeter" and prec == NBODY_PREC_MIXED) else TOL[prec]["j"]
+    for ipl, jl in SHAPES:
+        for c in range(5):
+            g.set_tuning(ipl, jl, size_class=c)
+        for il, (ra, rj, rp) in cases:
+            note(f"  shape ({ipl}, {jl}) n={len(il)}")
+            acc, jerk, pot = g.force_jerk(il, t)
+            ea = relerr(acc.T.cpu().numpy(), ra).max()
+            ej = relerr(jerk.T.cpu().numpy(), rj).max()
+            ep = relerr(pot.cpu().numpy(), rp).max()
+            assert ea <= scale * TOL[prec]["a"], (ipl, jl, len(il), ea)
+            assert ej <= scale * jtol, (ipl, jl, len(il), ej)
+            assert ep <= scale * TOL[prec]["p"], (ipl, jl, len(il), ep)
+    g.close()
+
+
 @pytest.mark.parametrize("prec", PREC, ids=PID)
 def test_near_field_overflow_keeps_every_pair(prec):
     # 40 particles within 1e-6 of one point, eps = 1e-4: for each of them all
