@@ -316,12 +316,22 @@ def test_explicit_block_step_matches_oracle_fp64():
 
 
 @pytest.mark.parametrize("prec", PREC, ids=PID)
-def test_step_block_matches_oracle(prec):
-    note(f"step_block prec={prec}")
+@pytest.mark.parametrize("tuning", ["default", "one-lane", "reversed"])
+def test_step_block_matches_oracle(prec, tuning):
+    # the default shapes give every class its own lane-group width; "one-lane"
+    # runs every class on one-lane-per-i kernels, "reversed" swaps the lane
+    # groups of the small classes, so the shared lane-group launch serves other
+    # widths than by default
+    note(f"step_block prec={prec} tuning={tuning}")
     x, v, m = plummer(2000, 1006)
     eps = 1 / 256
     prm = oracle.params(eps, dt_min_log2=-20, dt_max_log2=-3)
     g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    shapes = {"one-lane": [(1, 1), (2, 1), (1, 1), (2, 1), (1, 1)],
+              "reversed": [(1, 1), (1, 256), (1, 64), (1, 16), (1, 4)]}.get(tuning)
+    if shapes:
+        for c, (ipl, jl) in enumerate(shapes):
+            g.set_tuning(ipl, jl, size_class=c)
     g.init()
     xg, vg, ag, jg, tg, dtg = g.host_state()
     ref = oracle.System.from_state(xg, vg, m, ag, jg, tg, dtg, prm)
