@@ -351,6 +351,28 @@ def ensemble_bench(torch, n_clusters: int, t_short: float, t_full: float, per_cl
     return res
 
 
+def fused_bench(system, mask: int, reps: int):
+    """Block steps to T_END with in-kernel prediction for the classes in
+    `mask` against the prediction pass, alternating, from the same state."""
+    g, torch = system.g, system.torch
+    times = {0: [], mask: []}
+    for _ in range(reps):
+        for mk in (0, mask):
+            g.set_fused_predict(mk)
+            system.restore()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g.run_until(T_END)
+            torch.cuda.synchronize()
+            times[mk].append((time.perf_counter() - t0) * 1e3)
+    g.set_fused_predict(0)
+    out = {"workload": f"plummer_N{g.n}_blocksteps_to_t{T_END}", "fused_class_mask": mask,
+           "ms_prediction_pass": times[0], "ms_in_kernel": times[mask],
+           "ratio_in_kernel_over_pass": min(times[mask]) / min(times[0])}
+    log(f"fused prediction mask {mask}: {out}")
+    return out
+
+
 def salpeter_bench(torch, n: int, t_end: float, cpu_check: bool):
     """Unequal masses: a Plummer sphere with Salpeter masses (0.1-100, seed
     1017), eps = 1/1024, mixed form (its per-pair near-field variant): the full
@@ -570,6 +592,11 @@ def main():
                     help="also fit and check the per-step performance model on these N "
                          "(comma separated, e.g. 1024,4096,16384,65536,196608)")
     ap.add_argument("--perfmodel-t", type=float, default=1.0)
+    ap.add_argument("--fused-mask", type=int, default=0b11100)
+    ap.add_argument("--fused", type=int, default=0,
+                    help="also time block steps with in-kernel prediction for the size "
+                         "classes in this bit mask (e.g. 28 = classes 2-4), against the "
+                         "prediction pass, this many times each")
     ap.add_argument("--salpeter", type=int, default=0,
                     help="also run a Salpeter-mass Plummer sphere of this N (e.g. 196608)")
     ap.add_argument("--sweep-only", type=int, default=0,
@@ -681,6 +708,7 @@ def main():
         if args.salpeter else None
     extra_pm = perfmodel_bench(torch, [int(q) for q in args.perfmodel.split(",")],
                                args.perfmodel_t) if args.perfmodel else None
+    extra_fused = fused_bench(mixed, args.fused_mask, args.fused) if args.fused else None
 
     line = {
         "metric": METRIC,
@@ -718,6 +746,7 @@ def main():
                      "frac": achieved / PEAK_FP32, "traffic": sweep_traffic(),
                      "flops_per_interaction": FLOPS_PER_INTERACTION},
         "fp64": fp64,
+        "fused_prediction": extra_fused,
         "cpu_baseline": cpu,
         "accuracy": accuracy,
         "energy": energy,

@@ -275,6 +275,22 @@ int nbody_get_tuning(const nbody_ctx *ctx, nbody_tuning *out);
 int nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *tuning);
 
 /*
+ * In-kernel prediction.  Bit k of class_mask: in the block steps of a single
+ * cluster (nbody_step_block, nbody_run_until), blocks of size class k whose
+ * tuned shape is a lane-group shape (j_lanes 4 to 256) skip the prediction
+ * pass over all N particles; their force launch predicts each j- and
+ * i-particle it reads from the state instead, with the same arithmetic (the
+ * prediction of section 4.1, step 3, done where the force pipeline reads the
+ * particle, as GRAPE predicts the j-particles on the board: section 4.4,
+ * steps 3 and 4), so results are bitwise the same either way.  Ensembles and
+ * the explicit calls always use the prediction pass.  The default is 0 (every
+ * block uses the prediction pass, which is faster on this hardware); the
+ * option is for experiments and for workloads whose blocks are tiny.  Drops
+ * the captured graph.  EINVAL for bits beyond the classes.
+ */
+int nbody_set_fused_predict(nbody_ctx *ctx, int32_t class_mask);
+
+/*
  * Autotuner: for blocks of n_probe particles per cluster (1 <= n_probe; a
  * cluster smaller than n_probe uses all its particles), time one force
  * evaluation with every supported launch shape of the class that block size

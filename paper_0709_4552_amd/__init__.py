@@ -161,6 +161,10 @@ class NBody:
         t = _lib.nbody_tuning(size_class, i_per_lane, j_lanes, j_tile, grid)
         check(_lib.nbody_set_tuning(self.ctx, t), "nbody_set_tuning")
 
+    def set_fused_predict(self, class_mask: int):
+        """Size classes whose block steps predict inside the force kernel."""
+        check(_lib.nbody_set_fused_predict(self.ctx, class_mask), "nbody_set_fused_predict")
+
     def autotune(self, n_probe: int):
         """Pick the fastest launch shape for blocks of n_probe; returns (tuning, ms)."""
         rc, t, ms = _lib.nbody_autotune(self.ctx, n_probe)

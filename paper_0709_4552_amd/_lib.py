@@ -30,7 +30,7 @@ EXPORTS = (
     "nbody_strerror", "nbody_create", "nbody_destroy", "nbody_init", "nbody_predict",
     "nbody_force_jerk", "nbody_correct", "nbody_step_block", "nbody_run_until", "nbody_sync",
     "nbody_get_stats", "nbody_read_predicted", "nbody_get_tuning", "nbody_set_tuning",
-    "nbody_autotune", "nbody_save", "nbody_load",
+    "nbody_autotune", "nbody_save", "nbody_load", "nbody_set_fused_predict",
 )
 
 
@@ -117,6 +117,7 @@ def load(path: str = LIB_PATH):
     L.nbody_read_predicted.argtypes = [vp, vp, vp]
     L.nbody_get_tuning.argtypes = [vp, ctypes.POINTER(nbody_tuning)]
     L.nbody_set_tuning.argtypes = [vp, ctypes.POINTER(nbody_tuning)]
+    L.nbody_set_fused_predict.argtypes = [vp, ctypes.c_int32]
     L.nbody_autotune.argtypes = [vp, i64, ctypes.POINTER(nbody_tuning), ctypes.POINTER(d)]
     L.nbody_save.argtypes = [vp, ctypes.c_char_p]
     L.nbody_load.argtypes = [vp, ctypes.c_char_p]
@@ -210,6 +211,10 @@ def nbody_get_tuning(ctx: int, size_class: int = 0):
 
 def nbody_set_tuning(ctx: int, tuning: nbody_tuning) -> int:
     return load().nbody_set_tuning(ctypes.c_void_p(ctx), ctypes.byref(tuning))
+
+
+def nbody_set_fused_predict(ctx: int, class_mask: int) -> int:
+    return load().nbody_set_fused_predict(ctypes.c_void_p(ctx), int(class_mask))
 
 
 def nbody_autotune(ctx: int, n_probe: int):

@@ -67,7 +67,7 @@ struct ForceOcc {
     static constexpr int kMinBlocks = (MIXED && I == 1 && LJ == 1) ? 5 : 1;
 };
 
-template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL, bool PM>
+template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL, bool PM, bool FUSE>
 __device__ __forceinline__ void force_body(const ForceArgs &fa) {
     static_assert(MIXED || !PM, "per-pair near test only in the mixed form");
     static_assert(LJ == 1 || LJ == 4 || LJ == 16 || LJ == 64 || LJ == 256, "J_LANES");
@@ -100,22 +100,42 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
     // per-lane list of near pairs found in the current tile step (offset in it)
     constexpr int kNearCap = 8;
     __shared__ uint16_t sNear[MIXED ? I * kNearCap * kWG : 1];
-    // j-particle t of the current tile step: from LDS, or (DIRECT) from global
-    // memory with massless far-away padding past the end of the slice
-    auto jP = [&](int64_t tb, int64_t j1, int t) -> float4 {
-        if (!DIRECT)
-            return sP[t];
-        return tb + t < j1 ? fa.jb.P[tb + t] : make_float4(1e18f, 1e18f, 1e18f, 0.f);
+    // Particle j's record: from the j-buffer, or (fused) predicted here from
+    // the state to tick T with the prediction pass's own arithmetic.
+    bool fused = false;
+    auto fetch_m = [&](int64_t j, int64_t T, float4 &P, float4 &Q, float2 &R) {
+        if (FUSE && fused) {
+            predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, j, T, P, Q, R);
+        } else {
+            P = fa.jb.P[j];
+            Q = fa.jb.Q[j];
+            R = fa.jb.R[j];
+        }
     };
-    auto jQ = [&](int64_t tb, int64_t j1, int t) -> float4 {
-        if (!DIRECT)
-            return sQ[t];
-        return tb + t < j1 ? fa.jb.Q[tb + t] : make_float4(0.f, 0.f, 0.f, 0.f);
+    auto fetch_d = [&](int64_t j, int64_t T, double2 &A, double2 &B, double2 &C, double &D) {
+        if (FUSE && fused) {
+            predict_fp64(fa.st, fa.tick, j, T, A, B, C, D);
+        } else {
+            A = fa.jb.A[j];
+            B = fa.jb.B[j];
+            C = fa.jb.C[j];
+            D = fa.jb.D[j];
+        }
     };
-    auto jR = [&](int64_t tb, int64_t j1, int t) -> float2 {
-        if (!DIRECT)
-            return sR[t];
-        return tb + t < j1 ? fa.jb.R[tb + t] : make_float2(0.f, 0.f);
+    // j-particle t of the current tile step: from LDS, or (DIRECT) fetched per
+    // lane, with massless far-away padding past the end of the slice
+    auto jPQR = [&](int64_t tb, int64_t j1, int t, int64_t T, float4 &p, float4 &q, float2 &r) {
+        if (!DIRECT) {
+            p = sP[t];
+            q = sQ[t];
+            r = sR[t];
+        } else if (tb + t < j1) {
+            fetch_m(tb + t, T, p, q, r);
+        } else {
+            p = make_float4(1e18f, 1e18f, 1e18f, 0.f);
+            q = make_float4(0.f, 0.f, 0.f, 0.f);
+            r = make_float2(0.f, 0.f);
+        }
     };
 
     const int tid = threadIdx.x;
@@ -131,8 +151,11 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
 
     __shared__ int64_t s_item;
     // the plan picks one class; a launch serves every class sharing its shape
-    if (((fa.cls_mask >> uniform_i32(*fa.cls)) & 1) == 0)
+    const int cls_now = uniform_i32(*fa.cls);
+    if (((fa.cls_mask >> cls_now) & 1) == 0)
         return;
+    if (FUSE)
+        fused = ((fa.fused_mask >> cls_now) & 1) != 0;
     const int64_t total = uniform_i64(*fa.total_items);
     // first round static (item = workgroup index); only when there are more
     // items than workgroups do finished workgroups pop further items from the
@@ -172,6 +195,7 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
         const int64_t j0 = cb + (int64_t)js * jl;
         const int64_t j1 = min(ce, j0 + jl);
         const int64_t slot0 = fa.slots_at_offsets ? cb : 0;
+        const int64_t Tc = (FUSE && fused) ? uniform_i64(fa.t_cur[c]) : 0;
 
         // ---- i-particles into registers
         bool valid[I];
@@ -191,8 +215,9 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
             }
             gi[ii] = i;
             if (MIXED) {
-                const float4 p = fa.jb.P[i], q = fa.jb.Q[i];
-                const float2 r = fa.jb.R[i];
+                float4 p, q;
+                float2 r;
+                fetch_m(i, Tc, p, q, r);
                 xh[ii] = p.x; yh[ii] = p.y; zh[ii] = p.z; mi[ii] = p.w;
                 xl[ii] = q.x; yl[ii] = q.y; zl[ii] = q.z; vxi[ii] = q.w;
                 vyi[ii] = r.x; vzi[ii] = r.y;
@@ -207,9 +232,11 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                 }
                 scrit[ii] = sc;
             } else {
-                const double2 a = fa.jb.A[i], b = fa.jb.B[i], cc = fa.jb.C[i];
+                double2 a, b, cc;
+                double dd;
+                fetch_d(i, Tc, a, b, cc, dd);
                 X[ii] = a.x; Y[ii] = a.y; Z[ii] = b.x; M[ii] = b.y;
-                VX[ii] = cc.x; VY[ii] = cc.y; VZ[ii] = fa.jb.D[i];
+                VX[ii] = cc.x; VY[ii] = cc.y; VZ[ii] = dd;
             }
         }
 
@@ -245,9 +272,7 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                 const int64_t j = tb + t;
                 if (MIXED) {
                     if (j < j1) {
-                        sP[t] = fa.jb.P[j];
-                        sQ[t] = fa.jb.Q[j];
-                        sR[t] = fa.jb.R[j];
+                        fetch_m(j, Tc, sP[t], sQ[t], sR[t]);
                     } else {  // massless padding far away: contributes exactly 0
                         sP[t] = make_float4(1e18f, 1e18f, 1e18f, 0.f);
                         sQ[t] = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -255,10 +280,7 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                     }
                 } else {
                     if (j < j1) {
-                        sA[t] = fa.jb.A[j];
-                        sB[t] = fa.jb.B[j];
-                        sC[t] = fa.jb.C[j];
-                        sD[t] = fa.jb.D[j];
+                        fetch_d(j, Tc, sA[t], sB[t], sC[t], sD[t]);
                     } else {
                         sA[t] = make_double2(1e18, 1e18);
                         sB[t] = make_double2(1e18, 0.0);
@@ -285,9 +307,7 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
 #pragma unroll
                         for (int g = 0; g < G; g++) {
                             const int t = lj + (ch * CHJ + u + g) * LJ;
-                            p[g] = jP(tb, j1, t);
-                            q[g] = jQ(tb, j1, t);
-                            r[g] = jR(tb, j1, t);
+                            jPQR(tb, j1, t, Tc, p[g], q[g], r[g]);
                         }
                         bool nr[G][I];
                         bool any = false;
@@ -386,9 +406,9 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                         }
                         if (j >= j1)
                             continue;
-                        const float4 p = jP(tb, j1, t);
-                        const float4 q = jQ(tb, j1, t);
-                        const float2 r = jR(tb, j1, t);
+                        float4 p, q;
+                        float2 r;
+                        jPQR(tb, j1, t, Tc, p, q, r);
                         const double ex = ((double)p.x - (double)xh[ii]) + ((double)q.x - (double)xl[ii]);
                         const double ey = ((double)p.y - (double)yh[ii]) + ((double)q.y - (double)yl[ii]);
                         const double ez = ((double)p.z - (double)zh[ii]) + ((double)q.z - (double)zl[ii]);
@@ -418,11 +438,14 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                     double vz;
                     if (DIRECT) {
                         const int64_t j = tb + t;
-                        const bool in = j < j1;
-                        a = in ? fa.jb.A[j] : make_double2(1e18, 1e18);
-                        b = in ? fa.jb.B[j] : make_double2(1e18, 0.0);
-                        cv = in ? fa.jb.C[j] : make_double2(0.0, 0.0);
-                        vz = in ? fa.jb.D[j] : 0.0;
+                        if (j < j1) {
+                            fetch_d(j, Tc, a, b, cv, vz);
+                        } else {
+                            a = make_double2(1e18, 1e18);
+                            b = make_double2(1e18, 0.0);
+                            cv = make_double2(0.0, 0.0);
+                            vz = 0.0;
+                        }
                     } else {
                         a = sA[t];
                         b = sB[t];
@@ -558,23 +581,24 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
 // One lane per i-particle (one or two per lane): a launch of its own.
 template <int I, int LJ, int JT, bool MIXED, bool POT, bool EXCL, bool PM>
 __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_force(ForceArgs fa) {
-    force_body<I, LJ, JT, MIXED, POT, EXCL, PM>(fa);
+    force_body<I, LJ, JT, MIXED, POT, EXCL, PM, false>(fa);
 }
 
 // Lane groups of 4, 16, 64 or 256 per i-particle: one launch serves every
 // class that uses any of them, with the group width of the class the plan
 // picked (log2 in fa.cls_lj), so a block step needs at most two force
-// launches whatever shapes the classes were tuned to.
+// launches whatever shapes the classes were tuned to.  Classes in
+// fa.fused_mask predict their particles in the kernel.
 template <int JT, bool MIXED, bool POT, bool EXCL, bool PM>
 __global__ __launch_bounds__(kWG) void k_force_groups(ForceArgs fa) {
     const int cls = uniform_i32(*fa.cls);
     if (((fa.cls_mask >> cls) & 1) == 0)
         return;
     switch ((fa.cls_lj >> (4 * cls)) & 15u) {
-        case 2: force_body<1, 4, JT, MIXED, POT, EXCL, PM>(fa); break;
-        case 4: force_body<1, 16, JT, MIXED, POT, EXCL, PM>(fa); break;
-        case 6: force_body<1, 64, JT, MIXED, POT, EXCL, PM>(fa); break;
-        case 8: force_body<1, 256, JT, MIXED, POT, EXCL, PM>(fa); break;
+        case 2: force_body<1, 4, JT, MIXED, POT, EXCL, PM, true>(fa); break;
+        case 4: force_body<1, 16, JT, MIXED, POT, EXCL, PM, true>(fa); break;
+        case 6: force_body<1, 64, JT, MIXED, POT, EXCL, PM, true>(fa); break;
+        case 8: force_body<1, 256, JT, MIXED, POT, EXCL, PM, true>(fa); break;
         default: atomicOr(fa.err, kErrPlan); break;
     }
 }

@@ -47,41 +47,26 @@ __global__ void k_iota_i32(int32_t *p, int64_t n) {
 }
 
 // ---------------------------------------------------------------- predictor
-// Third-order Taylor prediction of particle i to time T (section 4.1, step 3),
-// written to the j-particle buffer.
+// Prediction of particle i to time T written to the j-particle buffer (the
+// arithmetic is shared with the force kernels' in-kernel prediction).
 template <int MIXED>
 __device__ inline void predict_one(const State &st, const Params &pr, const JBuf &jb, int64_t i,
-                                   int64_t tick_i, int64_t T) {
-    const double d = (double)(T - tick_i) * pr.tick;
-    const double h = 0.5 * d, s6 = d * (1.0 / 6.0);
-    const double ax = st.ax[i], ay = st.ay[i], az = st.az[i];
-    const double jx = st.jx[i], jy = st.jy[i], jz = st.jz[i];
-    const double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
-    // xp = x + d (v + d (a/2 + d j/6)),  vp = v + d (a + d j/2)
-    const double xp = fma(d, fma(d, fma(s6, jx, 0.5 * ax), vx), st.x[i]);
-    const double yp = fma(d, fma(d, fma(s6, jy, 0.5 * ay), vy), st.y[i]);
-    const double zp = fma(d, fma(d, fma(s6, jz, 0.5 * az), vz), st.z[i]);
-    const double vxp = fma(d, fma(h, jx, ax), vx);
-    const double vyp = fma(d, fma(h, jy, ay), vy);
-    const double vzp = fma(d, fma(h, jz, az), vz);
-    const double m = st.m[i];
+                                   int64_t T) {
     if (MIXED) {
-        // hi on a fixed grid: differences of hi parts are exact, so the
-        // rounding of x_j - x_i does not depend on i's low bits
-        const float xh = (float)(rint(xp * pr.grid_inv) * pr.grid_q);
-        const float yh = (float)(rint(yp * pr.grid_inv) * pr.grid_q);
-        const float zh = (float)(rint(zp * pr.grid_inv) * pr.grid_q);
-        const float xl = (float)(xp - (double)xh);
-        const float yl = (float)(yp - (double)yh);
-        const float zl = (float)(zp - (double)zh);
-        jb.P[i] = make_float4(xh, yh, zh, (float)m);
-        jb.Q[i] = make_float4(xl, yl, zl, (float)vxp);
-        jb.R[i] = make_float2((float)vyp, (float)vzp);
+        float4 P, Q;
+        float2 R;
+        predict_mixed(st, pr.tick, pr.grid_q, pr.grid_inv, i, T, P, Q, R);
+        jb.P[i] = P;
+        jb.Q[i] = Q;
+        jb.R[i] = R;
     } else {
-        jb.A[i] = make_double2(xp, yp);
-        jb.B[i] = make_double2(zp, m);
-        jb.C[i] = make_double2(vxp, vyp);
-        jb.D[i] = vzp;
+        double2 A, B, C;
+        double D;
+        predict_fp64(st, pr.tick, i, T, A, B, C, D);
+        jb.A[i] = A;
+        jb.B[i] = B;
+        jb.C[i] = C;
+        jb.D[i] = D;
     }
 }
 
@@ -100,7 +85,7 @@ __global__ __launch_bounds__(kWG) void k_predict(State st, Params pr, JBuf jb, c
                 continue;
             T = t_cur[c];
         }
-        predict_one<MIXED>(st, pr, jb, i, st.tick[i], T);
+        predict_one<MIXED>(st, pr, jb, i, T);
     }
 }
 
@@ -236,7 +221,7 @@ __global__ __launch_bounds__(kWG) void k_predict_compact(State st, Params pr, JB
     if (i < e) {
         const int64_t tk = st.tick[i];
         due = tk + dt_ticks(pr.lev_max, st.lev[i]) == T;
-        predict_one<MIXED>(st, pr, jb, i, tk, T);
+        predict_one<MIXED>(st, pr, jb, i, T);
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const unsigned long long bal = __ballot(due);
@@ -619,7 +604,7 @@ __global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params p
                                                               const int64_t *off, PlanDev pl,
                                                               int32_t *cursor, int32_t *i_list,
                                                               DevCtl *ctl, int64_t part_cap,
-                                                              ClassTable ct) {
+                                                              ClassTable ct, int32_t fused_mask) {
     constexpr int R = kPredictRounds, W = kWG / 64;
     __shared__ int32_t wcount[R * W];
     __shared__ int32_t base_s;
@@ -629,6 +614,15 @@ __global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params p
         plan_single_wave(off, pl, ctl, part_cap, ct, n, T, 1);
     if (n == 0)  // the same in every wave: they all read the same counts
         return;
+    // blocks of a class whose force kernel predicts in the kernel need no
+    // prediction pass: only the compaction (the planner's class rule)
+    int cls = kClasses - 1;
+    for (int k = 0; k < kClasses; k++)
+        if (n >= ct.min_n[k]) {
+            cls = k;
+            break;
+        }
+    const bool predict = ((fused_mask >> cls) & 1) == 0;
     const int64_t N = pr.n_total;
     const int64_t b = (int64_t)blockIdx.x * (R * kWG) + threadIdx.x;
     bool due[R];
@@ -637,9 +631,9 @@ __global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params p
         const int64_t i = b + r * kWG;
         due[r] = false;
         if (i < N) {
-            const int64_t tk = st.tick[i];
-            due[r] = tk + dt_ticks(pr.lev_max, st.lev[i]) == T;
-            predict_one<MIXED>(st, pr, jb, i, tk, T);
+            due[r] = st.tick[i] + dt_ticks(pr.lev_max, st.lev[i]) == T;
+            if (predict)
+                predict_one<MIXED>(st, pr, jb, i, T);
         }
     }
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -1108,17 +1102,17 @@ hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, 
 hipError_t launch_plan_predict_compact(const State &st, const Params &pr, const JBuf &jb,
                                        const int64_t *off, const PlanDev &pl, int32_t *cursor,
                                        int32_t *i_list, DevCtl *ctl, int64_t part_cap,
-                                       const ClassTable &ct, hipStream_t s) {
+                                       const ClassTable &ct, int32_t fused_mask, hipStream_t s) {
     if (pr.C != 1)
         return hipErrorInvalidValue;
     const int64_t per_wg = (int64_t)kPredictRounds * kWG;
     const unsigned g = (unsigned)((pr.n_total + per_wg - 1) / per_wg);
     if (pr.precision == NBODY_PREC_MIXED)
         hipLaunchKernelGGL(k_plan_predict_compact<1>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off,
-                           pl, cursor, i_list, ctl, part_cap, ct);
+                           pl, cursor, i_list, ctl, part_cap, ct, fused_mask);
     else
         hipLaunchKernelGGL(k_plan_predict_compact<0>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off,
-                           pl, cursor, i_list, ctl, part_cap, ct);
+                           pl, cursor, i_list, ctl, part_cap, ct, fused_mask);
     return hipGetLastError();
 }
 

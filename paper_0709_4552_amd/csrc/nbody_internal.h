@@ -156,7 +156,61 @@ struct ForceArgs {
     float near_frac;                // 0 disables the near field
     uint32_t cls_lj;                // lane-group launches: log2(j lanes) of class k
                                     // in bits 4k..4k+3
+    // in-kernel prediction (lane-group launches, one cluster): classes in
+    // fused_mask predict their j- and i-particles from the state to the
+    // cluster's block time t_cur[0] instead of reading the j-buffer
+    int32_t fused_mask;
+    State st;
+    const int64_t *t_cur;
+    double tick, grid_q, grid_inv;
 };
+
+// Third-order Taylor prediction of particle i to tick T (section 4.1, step
+// 3), as the j-buffer record the force kernels read: mixed P = (x_hi, y_hi,
+// z_hi, m), Q = (x_lo, y_lo, z_lo, vx), R = (vy, vz); FP64 A = (x, y),
+// B = (z, m), C = (vx, vy), D = vz.  The prediction pass and the force
+// kernels' in-kernel prediction both call these, so both give the same bits.
+__device__ inline void predict_terms(const State &st, double tick, int64_t i, int64_t T,
+                                     double &xp, double &yp, double &zp, double &vxp,
+                                     double &vyp, double &vzp) {
+    const double d = (double)(T - st.tick[i]) * tick;
+    const double h = 0.5 * d, s6 = d * (1.0 / 6.0);
+    const double ax = st.ax[i], ay = st.ay[i], az = st.az[i];
+    const double jx = st.jx[i], jy = st.jy[i], jz = st.jz[i];
+    const double vx = st.vx[i], vy = st.vy[i], vz = st.vz[i];
+    // xp = x + d (v + d (a/2 + d j/6)),  vp = v + d (a + d j/2)
+    xp = fma(d, fma(d, fma(s6, jx, 0.5 * ax), vx), st.x[i]);
+    yp = fma(d, fma(d, fma(s6, jy, 0.5 * ay), vy), st.y[i]);
+    zp = fma(d, fma(d, fma(s6, jz, 0.5 * az), vz), st.z[i]);
+    vxp = fma(d, fma(h, jx, ax), vx);
+    vyp = fma(d, fma(h, jy, ay), vy);
+    vzp = fma(d, fma(h, jz, az), vz);
+}
+
+__device__ inline void predict_mixed(const State &st, double tick, double grid_q, double grid_inv,
+                                     int64_t i, int64_t T, float4 &P, float4 &Q, float2 &R) {
+    double xp, yp, zp, vxp, vyp, vzp;
+    predict_terms(st, tick, i, T, xp, yp, zp, vxp, vyp, vzp);
+    // hi on a fixed grid: differences of hi parts are exact, so the rounding
+    // of x_j - x_i does not depend on i's low bits
+    const float xh = (float)(rint(xp * grid_inv) * grid_q);
+    const float yh = (float)(rint(yp * grid_inv) * grid_q);
+    const float zh = (float)(rint(zp * grid_inv) * grid_q);
+    P = make_float4(xh, yh, zh, (float)st.m[i]);
+    Q = make_float4((float)(xp - (double)xh), (float)(yp - (double)yh),
+                    (float)(zp - (double)zh), (float)vxp);
+    R = make_float2((float)vyp, (float)vzp);
+}
+
+__device__ inline void predict_fp64(const State &st, double tick, int64_t i, int64_t T,
+                                    double2 &A, double2 &B, double2 &C, double &D) {
+    double xp, yp, zp, vxp, vyp, vzp;
+    predict_terms(st, tick, i, T, xp, yp, zp, vxp, vyp, vzp);
+    A = make_double2(xp, yp);
+    B = make_double2(zp, st.m[i]);
+    C = make_double2(vxp, vyp);
+    D = vzp;
+}
 
 struct Shape {
     int i_per_lane;
@@ -232,10 +286,12 @@ hipError_t launch_predict_compact(const State &st, const Params &pr, const JBuf 
 hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, int32_t *n_act,
                        int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
                        int32_t host_n, int64_t host_t, int32_t count_stats, hipStream_t s);
+// fused_mask: classes whose force kernel predicts in the kernel; their blocks
+// skip the prediction pass (compaction only)
 hipError_t launch_plan_predict_compact(const State &st, const Params &pr, const JBuf &jb,
                                        const int64_t *off, const PlanDev &pl, int32_t *cursor,
                                        int32_t *i_list, DevCtl *ctl, int64_t part_cap,
-                                       const ClassTable &ct, hipStream_t s);
+                                       const ClassTable &ct, int32_t fused_mask, hipStream_t s);
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
                          const int32_t *s_max, hipStream_t s);
 hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Params &pr,

@@ -110,3 +110,4 @@ def test_null_context_is_rejected():
     assert L.nbody_destroy(None) == _lib.NBODY_EINVAL
     assert L.nbody_save(None, b"/tmp/x") == _lib.NBODY_EINVAL
     assert L.nbody_load(None, b"/tmp/x") == _lib.NBODY_EINVAL
+    assert L.nbody_set_fused_predict(None, 0) == _lib.NBODY_EINVAL

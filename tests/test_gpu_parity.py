@@ -350,6 +350,46 @@ def test_step_block_matches_oracle(prec, tuning):
     g.close()
 
 
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+@pytest.mark.parametrize("kind", ["equal", "salpeter"])
+def test_fused_prediction_is_bitwise_identical(prec, kind):
+    # blocks whose force launch predicts the particles in the kernel take the
+    # same bits as blocks that read the prediction pass's j-buffer: graph-
+    # replayed and eager steps, every class on lane-group shapes (class 0
+    # too) so every class can be fused; N = 3000 leaves ragged tiles
+    note(f"fused prediction prec={prec} kind={kind}")
+    N = 3000
+    x, v, m = plummer_salpeter(N, 1016) if kind == "salpeter" else plummer(N, 1016)
+    kw = dict(dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    runs = []
+    for mask in (0, 0b11111):
+        g = NBody(x, v, m, 1 / 256, **kw)
+        for c, jl in enumerate((4, 4, 16, 64, 256)):
+            g.set_tuning(1, jl, size_class=c)
+        g.set_fused_predict(mask)
+        g.init()
+        assert g.run_until(1 / 32) > 0
+        for _ in range(40):
+            g.step_block()
+        runs.append((g.host_state(), g.stats()))
+        g.close()
+    (ref, ref_stats), (got, got_stats) = runs
+    for r, q in zip(ref, got):
+        assert np.array_equal(r, q)
+    assert got_stats == ref_stats
+
+
+def test_fused_prediction_mask_checked():
+    x, v, m = plummer(500, 1017)
+    g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    for bad in (-1, 1 << 5):
+        with pytest.raises(NBodyError) as e:
+            g.set_fused_predict(bad)
+        assert e.value.code == _lib.NBODY_EINVAL
+    g.set_fused_predict(0)
+    g.close()
+
+
 def test_run_until_shared_steps_config1():
     note("config 1: N=1024 shared dt=1/256 32 steps fp64")
     x, v, m = plummer(1024, 1001)
