@@ -587,18 +587,20 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
 // Lane groups of 4, 16, 64 or 256 per i-particle: one launch serves every
 // class that uses any of them, with the group width of the class the plan
 // picked (log2 in fa.cls_lj), so a block step needs at most two force
-// launches whatever shapes the classes were tuned to.  Classes in
-// fa.fused_mask predict their particles in the kernel.
-template <int JT, bool MIXED, bool POT, bool EXCL, bool PM>
+// launches whatever shapes the classes were tuned to.  The FUSE instance,
+// launched only when fa.fused_mask is not empty, lets the classes in it
+// predict their particles in the kernel (the other instance carries no code
+// for that).
+template <int JT, bool MIXED, bool POT, bool EXCL, bool PM, bool FUSE>
 __global__ __launch_bounds__(kWG) void k_force_groups(ForceArgs fa) {
     const int cls = uniform_i32(*fa.cls);
     if (((fa.cls_mask >> cls) & 1) == 0)
         return;
     switch ((fa.cls_lj >> (4 * cls)) & 15u) {
-        case 2: force_body<1, 4, JT, MIXED, POT, EXCL, PM, true>(fa); break;
-        case 4: force_body<1, 16, JT, MIXED, POT, EXCL, PM, true>(fa); break;
-        case 6: force_body<1, 64, JT, MIXED, POT, EXCL, PM, true>(fa); break;
-        case 8: force_body<1, 256, JT, MIXED, POT, EXCL, PM, true>(fa); break;
+        case 2: force_body<1, 4, JT, MIXED, POT, EXCL, PM, FUSE>(fa); break;
+        case 4: force_body<1, 16, JT, MIXED, POT, EXCL, PM, FUSE>(fa); break;
+        case 6: force_body<1, 64, JT, MIXED, POT, EXCL, PM, FUSE>(fa); break;
+        case 8: force_body<1, 256, JT, MIXED, POT, EXCL, PM, FUSE>(fa); break;
         default: atomicOr(fa.err, kErrPlan); break;
     }
 }
@@ -624,31 +626,33 @@ KernelFn pick(int mixed, int pot, int excl, int pm) {
     }
 }
 
-template <int JT>
+template <int JT, bool FUSE>
 KernelFn pick_groups(int mixed, int pot, int excl, int pm) {
     const int key = mixed ? 4 + (pm ? 4 : 0) + pot * 2 + excl : pot * 2 + excl;
     switch (key) {
-        case 0: return k_force_groups<JT, false, false, false, false>;
-        case 1: return k_force_groups<JT, false, false, true, false>;
-        case 2: return k_force_groups<JT, false, true, false, false>;
-        case 3: return k_force_groups<JT, false, true, true, false>;
-        case 4: return k_force_groups<JT, true, false, false, false>;
-        case 5: return k_force_groups<JT, true, false, true, false>;
-        case 6: return k_force_groups<JT, true, true, false, false>;
-        case 7: return k_force_groups<JT, true, true, true, false>;
-        case 8: return k_force_groups<JT, true, false, false, true>;
-        case 9: return k_force_groups<JT, true, false, true, true>;
-        case 10: return k_force_groups<JT, true, true, false, true>;
-        default: return k_force_groups<JT, true, true, true, true>;
+        case 0: return k_force_groups<JT, false, false, false, false, FUSE>;
+        case 1: return k_force_groups<JT, false, false, true, false, FUSE>;
+        case 2: return k_force_groups<JT, false, true, false, false, FUSE>;
+        case 3: return k_force_groups<JT, false, true, true, false, FUSE>;
+        case 4: return k_force_groups<JT, true, false, false, false, FUSE>;
+        case 5: return k_force_groups<JT, true, false, true, false, FUSE>;
+        case 6: return k_force_groups<JT, true, true, false, false, FUSE>;
+        case 7: return k_force_groups<JT, true, true, true, false, FUSE>;
+        case 8: return k_force_groups<JT, true, false, false, true, FUSE>;
+        case 9: return k_force_groups<JT, true, false, true, true, FUSE>;
+        case 10: return k_force_groups<JT, true, true, false, true, FUSE>;
+        default: return k_force_groups<JT, true, true, true, true, FUSE>;
     }
 }
 
-KernelFn lookup(const Shape &sh, int mixed, int pot, int excl, int pm) {
+KernelFn lookup(const Shape &sh, int mixed, int pot, int excl, int pm, int fuse = 0) {
     if (sh.j_tile != 256)
         return nullptr;
     if (sh.j_lanes == 1 && sh.i_per_lane == 1) return pick<1, 1, 256>(mixed, pot, excl, pm);
     if (sh.j_lanes == 1 && sh.i_per_lane == 2) return pick<2, 1, 256>(mixed, pot, excl, pm);
-    if (force_shape_grouped(sh)) return pick_groups<256>(mixed, pot, excl, pm);
+    if (force_shape_grouped(sh))
+        return fuse ? pick_groups<256, true>(mixed, pot, excl, pm)
+                    : pick_groups<256, false>(mixed, pot, excl, pm);
     return nullptr;
 }
 
@@ -681,7 +685,7 @@ int force_occupancy(const Shape &sh, int mixed, int want_pot, int exclude_self, 
 
 hipError_t launch_force(const Shape &sh, int mixed, int want_pot, int exclude_self, int pair_mass,
                         const ForceArgs &fa, int grid, hipStream_t s) {
-    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self, pair_mass);
+    KernelFn fn = lookup(sh, mixed, want_pot, exclude_self, pair_mass, fa.fused_mask != 0);
     if (!fn)
         return hipErrorInvalidValue;
     ForceArgs a = fa;
