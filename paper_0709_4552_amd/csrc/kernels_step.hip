@@ -244,14 +244,6 @@ __global__ __launch_bounds__(kWG) void k_predict_compact(State st, Params pr, JB
 }
 
 // ---------------------------------------------------------------- planning
-// Builds the work list of one force evaluation: cluster c gets
-// ceil(n_c / ib) i-blocks times S_c j-slices.  The shape class (and so ib)
-// follows the mean block size of the active clusters.  One cluster: S is the
-// value in [1, kMaxSlices] that minimises the modelled time
-// ceil(items / plan_grid) * (tiles per slice + 1).  Several clusters: S_c
-// follows the cluster's share of the work so the whole evaluation has about
-// 4*grid items; the force kernel's work queue balances the rest.  One
-// workgroup.
 // Next block of cluster c from its level counts (one thread).  n = 0 when the
 // cluster's next time lies beyond t_end; then the cluster's time stays.
 __device__ inline int32_t block_from_levels(const Params &pr, const PlanDev &pl, int c,
@@ -289,6 +281,12 @@ __device__ int64_t block_exclusive_scan(int64_t v, int64_t *tmp, int64_t *total)
     return incl - v;
 }
 
+// Work list of one force evaluation of an ensemble (several clusters; one
+// cluster is planned by plan_single_wave): cluster c gets ceil(n_c / ib)
+// i-blocks times S_c j-slices.  The shape class (and so ib) follows the mean
+// block size of the active clusters; S_c follows the cluster's share of the
+// work so the whole evaluation has about 4*grid items, and the force kernel's
+// work queue balances the rest.  One workgroup.
 __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t *off, PlanDev pl,
                                                        int32_t *n_act, int64_t *t_next,
                                                        DevCtl *ctl, int64_t part_cap,
@@ -299,7 +297,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
     __shared__ double dred[kPlanThreads];
     __shared__ int64_t carry_items, carry_parts;
     __shared__ int s_fallback;
-    __shared__ int s_best_S;
     const int t = threadIdx.x;
     const int C = pr.C;
     const int64_t t_end = ctl->t_end_tick;
@@ -364,33 +361,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
     const int64_t ib_size = ct.ib[cls];
     const int64_t grid_res = ct.grid[cls];
     const int32_t j_tile = ct.jt[cls];
-    // one cluster: choose S by the cost model (every thread tries one S)
-    if (C == 1) {
-        const int64_t n = pl.n_cur[0];
-        const int64_t Nc = off[1] - off[0];
-        const int64_t tiles = (Nc + j_tile - 1) / j_tile;
-        const int64_t nib = (n + ib_size - 1) / ib_size;
-        const int64_t grid = plan_grid(grid_res, nib, tiles);
-        const int64_t S = t + 1;
-        int64_t key = INT64_MAX;
-        if (n > 0 && S <= tiles && S <= kMaxSlices && (S == 1 || S * n <= part_cap)) {
-            const int64_t tps = (tiles + S - 1) / S;
-            const int64_t Seff = (tiles + tps - 1) / tps;
-            const int64_t waves = (nib * Seff + grid - 1) / grid;
-            // time ~ waves of items x (tiles per slice + item overhead); ties -> smaller S
-            key = ((waves * (tps + 1)) << 11) | (S - 1);
-        }
-        tmp[t] = key;
-        __syncthreads();
-        for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
-            if (t < o && tmp[t + o] < tmp[t])
-                tmp[t] = tmp[t + o];
-            __syncthreads();
-        }
-        if (t == 0)
-            s_best_S = tmp[0] == INT64_MAX ? 1 : (int)(tmp[0] & 2047) + 1;
-        __syncthreads();
-    }
     if (t == 0)
         s_fallback = 0;
     __syncthreads();
@@ -413,9 +383,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
                     const int64_t tiles = (Nc + j_tile - 1) / j_tile;
                     int64_t s = 1;
                     if (!uniform_i32(s_fallback)) {
-                        if (C == 1) {
-                            s = uniform_i32(s_best_S);
-                        } else if (W > 0.0) {
+                        if (W > 0.0) {
                             const double share = (double)n * (double)Nc / W;
                             s = (int64_t)ceil(4.0 * (double)grid_res * share / (double)nib);
                         }
