@@ -286,7 +286,8 @@ int nbody_set_tuning(nbody_ctx *ctx, const nbody_tuning *tuning);
  * the explicit calls always use the prediction pass.  The default is 0 (every
  * block uses the prediction pass, which is faster on this hardware); the
  * option is for experiments and for workloads whose blocks are tiny.  Drops
- * the captured graph.  EINVAL for bits beyond the classes.
+ * the captured graph; not stored by nbody_save.  EINVAL for bits beyond the
+ * classes.
  */
 int nbody_set_fused_predict(nbody_ctx *ctx, int32_t class_mask);
 

@@ -379,6 +379,32 @@ def test_fused_prediction_is_bitwise_identical(prec, kind):
     assert got_stats == ref_stats
 
 
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_fused_prediction_unsoftened_and_ensembles(prec):
+    # eps = 0 (the self pair skipped) through the in-kernel prediction; an
+    # ensemble ignores the option (its blocks always use the prediction pass)
+    note(f"fused prediction eps=0 and ensemble prec={prec}")
+    cases = [dict(args=plummer(1500, 1018) + (0.0,), offs=None)]
+    x, v, m, offs = ensemble(5, 1019, 200, 900)
+    cases.append(dict(args=(x, v, m, 1 / 256), offs=offs))
+    for case in cases:
+        runs = []
+        for mask in (0, 0b11111):
+            g = NBody(*case["args"], dt_min_log2=-20, dt_max_log2=-4, precision=prec,
+                      cluster_offset=case["offs"])
+            for c, jl in enumerate((4, 4, 16, 64, 256)):
+                g.set_tuning(1, jl, size_class=c)
+            g.set_fused_predict(mask)
+            g.init()
+            g.run_until(1 / 64)
+            runs.append((g.host_state(), g.stats()))
+            g.close()
+        (ref, ref_stats), (got, got_stats) = runs
+        for r, q in zip(ref, got):
+            assert np.array_equal(r, q)
+        assert got_stats == ref_stats
+
+
 def test_fused_prediction_mask_checked():
     x, v, m = plummer(500, 1017)
     g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
