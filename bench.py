@@ -605,7 +605,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
-              "(how the path would shard is described in DESIGN.md)", file=sys.stderr)
+              "(a sharded design over RCCL is described with the documentation)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
