@@ -265,20 +265,39 @@ __device__ inline int32_t block_from_levels(const Params &pr, const PlanDev &pl,
     return n;
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: row
+// shifts by 1, 2, 4 and 8, then the row broadcasts of lanes 15 and 31.  Lanes
+// whose shifted source lies outside their row add 0.  Every lane takes part.
+__device__ inline int64_t wave_inclusive_scan(int64_t v) {
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
+// Exclusive prefix sum over the kPlanThreads threads of the workgroup, and the
+// total: wavefront scans, then a scan of the wave totals (two barriers; tmp
+// needs 2 * kPlanThreads / 64 entries).
 __device__ int64_t block_exclusive_scan(int64_t v, int64_t *tmp, int64_t *total) {
-    const int t = threadIdx.x;
-    tmp[t] = v;
+    constexpr int NW = kPlanThreads / 64;
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6;
+    const int64_t incl = wave_inclusive_scan(v);
+    if (lane == 63)
+        tmp[w] = incl;
     __syncthreads();
-    for (int o = 1; o < kPlanThreads; o <<= 1) {
-        const int64_t add = t >= o ? tmp[t - o] : 0;
-        __syncthreads();
-        tmp[t] += add;
-        __syncthreads();
+    if (w == 0) {
+        const int64_t tot = wave_inclusive_scan(lane < NW ? tmp[lane] : 0);
+        if (lane < NW)
+            tmp[NW + lane] = tot;
     }
-    const int64_t incl = tmp[t];
-    *total = tmp[kPlanThreads - 1];
     __syncthreads();
-    return incl - v;
+    const int64_t before = w > 0 ? tmp[NW + w - 1] : 0;
+    *total = tmp[2 * NW - 1];
+    __syncthreads();
+    return before + incl - v;
 }
 
 // Work list of one force evaluation of an ensemble (several clusters; one
@@ -328,27 +347,37 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
         n_local += n;
         act_local += n > 0;
     }
-    dred[t] = w_local;
-    tmp[t] = n_local;
-    __syncthreads();
-    for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
-        if (t < o) {
-            dred[t] += dred[t + o];
-            tmp[t] += tmp[t + o];
+    // totals over the workgroup: wavefront sums (DPP), then the 16 wave sums in
+    // order by thread 0
+    {
+        constexpr int NW = kPlanThreads / 64;
+        const int lane = t & 63, w = t >> 6;
+        const double wsum = group_sum<64>(w_local);
+        const int64_t nsum = wave_inclusive_scan(n_local);
+        const int64_t asum = wave_inclusive_scan(act_local);
+        if (lane == 63) {
+            dred[w] = wsum;
+            tmp[w] = nsum;
+            tmp[NW + w] = asum;
+        }
+        __syncthreads();
+        if (t == 0) {
+            double wt = 0.0;
+            int64_t nt = 0, at = 0;
+            for (int q = 0; q < NW; q++) {
+                wt += dred[q];
+                nt += tmp[q];
+                at += tmp[NW + q];
+            }
+            dred[NW] = wt;
+            tmp[2 * NW] = nt;
+            tmp[2 * NW + 1] = at;
         }
         __syncthreads();
     }
-    const double W = dred[0];
-    const int64_t n_sum = tmp[0];
-    __syncthreads();
-    tmp[t] = act_local;
-    __syncthreads();
-    for (int o = kPlanThreads / 2; o > 0; o >>= 1) {
-        if (t < o)
-            tmp[t] += tmp[t + o];
-        __syncthreads();
-    }
-    const int64_t n_active_clusters = tmp[0];
+    const double W = dred[kPlanThreads / 64];
+    const int64_t n_sum = tmp[2 * (kPlanThreads / 64)];
+    const int64_t n_active_clusters = tmp[2 * (kPlanThreads / 64) + 1];
     __syncthreads();
     // shape class from the mean block size
     const int64_t n_mean = n_active_clusters > 0 ? n_sum / n_active_clusters : 0;
