@@ -471,6 +471,38 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
 // One cluster, one wave (lane L looks at level L): the next block's time and
 // size from the level counts; n = 0 (and the time unchanged) when the next
 // time lies beyond t_end.  Every lane returns the same values.
+// Minimum and sum over the 64 lanes of a wave with DPP moves (quad swaps,
+// half-row and row mirrors, the row broadcasts of lanes 15 and 31; lanes a
+// step leaves out take the identity), read back from lane 63 so every lane
+// holds the result.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ inline int64_t dpp_min_step(int64_t v) {
+    const int64_t o = __builtin_amdgcn_update_dpp((int64_t)INT64_MAX, v, CTRL, ROW_MASK, 0xF, false);
+    return o < v ? o : v;
+}
+
+__device__ inline int64_t wave_min_i64(int64_t v) {
+    v = dpp_min_step<0xB1>(v);
+    v = dpp_min_step<0x4E>(v);
+    v = dpp_min_step<0x141>(v);
+    v = dpp_min_step<0x140>(v);
+    v = dpp_min_step<0x142, 0xA>(v);
+    v = dpp_min_step<0x143, 0xC>(v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), 63);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+__device__ inline int32_t wave_sum_i32(int32_t v) {
+    v += __builtin_amdgcn_update_dpp(0, v, 0xB1, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4E, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xF, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
 __device__ inline void next_block_wave(const Params &pr, const PlanDev &pl, int64_t t_end,
                                        int64_t *T_out, int64_t *n_out) {
     static_assert(kLevels == 64, "one level per lane");
@@ -479,16 +511,9 @@ __device__ inline void next_block_wave(const Params &pr, const PlanDev &pl, int6
     const int32_t cnt = in ? pl.lev_cnt[lane] : 0;
     const int sh = in ? pr.lev_max - lane : 0;
     const int64_t tnow = uniform_i64(pl.t_now[0]);
-    int64_t T = cnt > 0 ? level_next(tnow, sh) : INT64_MAX;
-    for (int o = 32; o > 0; o >>= 1) {
-        const int64_t other = __shfl_xor(T, o);
-        T = other < T ? other : T;
-    }
-    int32_t due = (cnt > 0 && T != INT64_MAX && (T & (((int64_t)1 << sh) - 1)) == 0) ? cnt : 0;
-    for (int o = 32; o > 0; o >>= 1)
-        due += __shfl_xor(due, o);
-    int64_t n = uniform_i32(due);
-    T = uniform_i64(T);
+    int64_t T = wave_min_i64(cnt > 0 ? level_next(tnow, sh) : INT64_MAX);
+    const int32_t due = (cnt > 0 && T != INT64_MAX && (T & (((int64_t)1 << sh) - 1)) == 0) ? cnt : 0;
+    int64_t n = wave_sum_i32(due);
     if (T == INT64_MAX || T > t_end) {
         n = 0;
         T = tnow;
@@ -529,10 +554,7 @@ __device__ inline void plan_single_wave(const int64_t *off, const PlanDev &pl, D
         const int64_t k2 = ((waves * (tps + 1)) << 11) | (S - 1);
         key = k2 < key ? k2 : key;
     }
-    for (int o = 32; o > 0; o >>= 1) {
-        const int64_t other = __shfl_xor(key, o);
-        key = other < key ? other : key;
-    }
+    key = wave_min_i64(key);
     if (lane == 0) {
         const int64_t S = key == INT64_MAX ? 1 : (key & 2047) + 1;
         int64_t items = 0, parts = 0;
