@@ -309,52 +309,63 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                             const int t = lj + (ch * CHJ + u + g) * LJ;
                             jPQR(tb, j1, t, Tc, p[g], q[g], r[g]);
                         }
-                        bool nr[G][I];
-                        bool any = false;
+                        float dx[G][I], dy[G][I], dz[G][I], wx[G][I], wy[G][I], wz[G][I];
+                        float sq[G][I], rw[G][I], rinv[G][I];
 #pragma unroll
                         for (int g = 0; g < G; g++) {
 #pragma unroll
                             for (int ii = 0; ii < I; ii++) {
-                                const float dx = (p[g].x - xh[ii]) + (q[g].x - xl[ii]);
-                                const float dy = (p[g].y - yh[ii]) + (q[g].y - yl[ii]);
-                                const float dz = (p[g].z - zh[ii]) + (q[g].z - zl[ii]);
-                                const float wx = q[g].w - vxi[ii];
-                                const float wy = r[g].x - vyi[ii];
-                                const float wz = r[g].y - vzi[ii];
-                                const float s = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, __builtin_fmaf(dx, dx, fa.eps2f)));
-                                const float rw = __builtin_fmaf(dz, wz, __builtin_fmaf(dy, wy, dx * wx));
-                                const bool near = s < (PM ? p[g].w * sc_eff[ii] : sc_eff[ii]);
-                                nr[g][ii] = near;
-                                any = any || near;
-                                float rinv = __builtin_amdgcn_rsqf(s);
+                                dx[g][ii] = (p[g].x - xh[ii]) + (q[g].x - xl[ii]);
+                                dy[g][ii] = (p[g].y - yh[ii]) + (q[g].y - yl[ii]);
+                                dz[g][ii] = (p[g].z - zh[ii]) + (q[g].z - zl[ii]);
+                                wx[g][ii] = q[g].w - vxi[ii];
+                                wy[g][ii] = r[g].x - vyi[ii];
+                                wz[g][ii] = r[g].y - vzi[ii];
+                                sq[g][ii] = __builtin_fmaf(dz[g][ii], dz[g][ii],
+                                            __builtin_fmaf(dy[g][ii], dy[g][ii],
+                                            __builtin_fmaf(dx[g][ii], dx[g][ii], fa.eps2f)));
+                                rw[g][ii] = __builtin_fmaf(dz[g][ii], wz[g][ii],
+                                            __builtin_fmaf(dy[g][ii], wy[g][ii], dx[g][ii] * wx[g][ii]));
+                                rinv[g][ii] = __builtin_amdgcn_rsqf(sq[g][ii]);
                                 if (EXCL)
-                                    rinv = s > 0.f ? rinv : 0.f;
-                                rinv = near ? 0.f : rinv;
-                                const float rinv2 = rinv * rinv;
-                                const float mr = p[g].w * rinv;
-                                const float mr3 = mr * rinv2;
-                                const float al = rw * rinv2;
-                                const float be = mr3 * al;
-                                if (POT)
-                                    fp[ii] += mr;
-                                fax[ii] = __builtin_fmaf(mr3, dx, fax[ii]);
-                                fay[ii] = __builtin_fmaf(mr3, dy, fay[ii]);
-                                faz[ii] = __builtin_fmaf(mr3, dz, faz[ii]);
-                                f1x[ii] = __builtin_fmaf(mr3, wx, f1x[ii]);
-                                f1y[ii] = __builtin_fmaf(mr3, wy, f1y[ii]);
-                                f1z[ii] = __builtin_fmaf(mr3, wz, f1z[ii]);
-                                f2x[ii] = __builtin_fmaf(be, dx, f2x[ii]);
-                                f2y[ii] = __builtin_fmaf(be, dy, f2y[ii]);
-                                f2z[ii] = __builtin_fmaf(be, dz, f2z[ii]);
+                                    rinv[g][ii] = sq[g][ii] > 0.f ? rinv[g][ii] : 0.f;
+                            }
+                        }
+                        // Is any pair of the group near?  With one threshold per i
+                        // the smallest s decides (one compare per group); the per-pair
+                        // flags and masks are only needed when the answer is yes.
+                        bool any = false;
+#pragma unroll
+                        for (int ii = 0; ii < I; ii++) {
+                            if (PM) {
+#pragma unroll
+                                for (int g = 0; g < G; g++)
+                                    any = any || sq[g][ii] < p[g].w * sc_eff[ii];
+                            } else {
+                                float smin = sq[0][ii];
+#pragma unroll
+                                for (int g = 1; g < G; g++)
+                                    smin = __builtin_fminf(smin, sq[g][ii]);
+                                any = any || smin < sc_eff[ii];
                             }
                         }
                         // The hint keeps this block inside the loop: rare with equal
                         // masses, it is frequent around heavy stars, and moved out of
                         // line it slowed the sweep of a Salpeter cluster by 6%.
                         if (__builtin_expect(__ballot(any) != 0ull, 1)) {
-                            // remember the pairs for the FP64 pass after the tile.
-                            // Masking stops once fewer than G slots are free, so the
-                            // pairs of one group always fit: every masked pair is kept.
+                            // mask the near pairs out of the FP32 sums and remember
+                            // them for the FP64 pass after the tile.  Masking stops
+                            // once fewer than G slots are free, so the pairs of one
+                            // group always fit: every masked pair is kept.
+                            bool nr[G][I];
+#pragma unroll
+                            for (int g = 0; g < G; g++) {
+#pragma unroll
+                                for (int ii = 0; ii < I; ii++) {
+                                    nr[g][ii] = sq[g][ii] < (PM ? p[g].w * sc_eff[ii] : sc_eff[ii]);
+                                    rinv[g][ii] = nr[g][ii] ? 0.f : rinv[g][ii];
+                                }
+                            }
 #pragma unroll
                             for (int g = 0; g < G; g++) {
 #pragma unroll
@@ -366,6 +377,28 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                                             sc_eff[ii] = 0.f;
                                     }
                                 }
+                            }
+                        }
+#pragma unroll
+                        for (int g = 0; g < G; g++) {
+#pragma unroll
+                            for (int ii = 0; ii < I; ii++) {
+                                const float rinv2 = rinv[g][ii] * rinv[g][ii];
+                                const float mr = p[g].w * rinv[g][ii];
+                                const float mr3 = mr * rinv2;
+                                const float al = rw[g][ii] * rinv2;
+                                const float be = mr3 * al;
+                                if (POT)
+                                    fp[ii] += mr;
+                                fax[ii] = __builtin_fmaf(mr3, dx[g][ii], fax[ii]);
+                                fay[ii] = __builtin_fmaf(mr3, dy[g][ii], fay[ii]);
+                                faz[ii] = __builtin_fmaf(mr3, dz[g][ii], faz[ii]);
+                                f1x[ii] = __builtin_fmaf(mr3, wx[g][ii], f1x[ii]);
+                                f1y[ii] = __builtin_fmaf(mr3, wy[g][ii], f1y[ii]);
+                                f1z[ii] = __builtin_fmaf(mr3, wz[g][ii], f1z[ii]);
+                                f2x[ii] = __builtin_fmaf(be, dx[g][ii], f2x[ii]);
+                                f2y[ii] = __builtin_fmaf(be, dy[g][ii], f2y[ii]);
+                                f2z[ii] = __builtin_fmaf(be, dz[g][ii], f2z[ii]);
                             }
                         }
                     }
