@@ -29,9 +29,10 @@
 // particle's stored acceleration) can be comparable to the whole force, where
 // FP32 rounding would exceed the error budget; such pairs are masked out of
 // the FP32 sums, recorded, and evaluated in FP64 after the tile.  With equal
-// masses the test is m_max/s > near_frac*|a_i| (one compare per pair); with a
-// mass spectrum (PM) it is m_j/s > near_frac*|a_i|, one multiply more, since
-// m_max would flag nearly every pair.  A lane records at most kNearCap pairs
+// masses the test is m_max/s > near_frac*|a_i|, asked once per group of j on
+// the smallest s (per-pair flags and masks only when a lane of the wave has a
+// near pair); with a mass spectrum (PM) it is m_j/s > near_frac*|a_i| per pair,
+// one multiply more, since m_max would flag nearly every pair.  A lane records at most kNearCap pairs
 // per tile; masking stops while a whole group of pairs still fits, so every
 // masked pair is recorded and none is lost.
 // FP64: every operation in double precision; s^{-1/2} from the hardware
