@@ -68,7 +68,8 @@ struct ClassTable {
 
 // Predicted j-particle buffer.
 //  mixed: P = (x_hi, y_hi, z_hi, m), Q = (x_lo, y_lo, z_lo, vx), R = (vy, vz)
-//         with x = x_hi + x_lo, x_hi = fl32(x), x_lo = fl32(x - x_hi)
+//         with x_hi = q rint(x/q) on the fixed grid q (so x_hi_j - x_hi_i is
+//         exact in FP32) and x_lo = fl32(x - x_hi)
 //  fp64 : A = (x, y), B = (z, m), C = (vx, vy), D = vz
 struct JBuf {
     float4 *P = nullptr;
