@@ -224,6 +224,60 @@ def test_near_field_overflow_keeps_every_pair(prec):
     g.close()
 
 
+def fp32_pair_terms_acc(x, m, eps, i, q=2.0 ** -16):
+    """Acceleration on i with every pair term in FP32 from double-single
+    differences (hi on the grid q, as the mixed kernel forms r), the terms
+    summed in FP64: the mixed form without its FP64 near field."""
+    hi = np.rint(x / q) * q
+    lo = (x - hi).astype(np.float32)
+    hi = hi.astype(np.float32)
+    d = ((hi - hi[i]) + (lo - lo[i])).astype(np.float32)
+    s = (d * d).sum(axis=1, dtype=np.float32) + np.float32(eps * eps)
+    rinv = (np.float32(1) / np.sqrt(s)).astype(np.float32)
+    mr3 = (m.astype(np.float32) * rinv * rinv * rinv).astype(np.float32)
+    f = (mr3[:, None] * d).astype(np.float64)
+    f[i] = 0.0
+    return f.sum(axis=0)
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_near_pairs_are_evaluated_in_fp64(prec):
+    # Three particles on a line, 1e-3 apart with the middle one off centre by
+    # 3e-6: its two pair terms (~500 each) cancel to |a| ~ 3, so FP32 rounding
+    # of those terms alone is far above the 1e-6 bar (checked below on the
+    # CPU), and only the FP64 near field meets it.  Evaluated at t = 0 so the
+    # positions are exactly the inputs.
+    note(f"near pairs in FP64 prec={prec}")
+    N = 2000
+    x, v, m = plummer(N, 1017)
+    x = x.copy()
+    c = np.array([0.0123, -0.0217, 0.0089])
+    x[100] = c - np.array([1e-3, 0.0, 0.0])
+    x[101] = c
+    x[102] = c + np.array([1e-3 + 3e-6, 0.0, 0.0])
+    eps = 1e-5
+    il = np.arange(N, dtype=np.int32)
+    ra, rj, rp = oracle.force(x, v, m, eps, il)
+    e32 = relerr(fp32_pair_terms_acc(x, m, eps, 101)[None, :], ra[101][None, :])[0]
+    assert e32 > 1e-5  # the configuration defeats FP32 pair terms
+    g = NBody(x, v, m, eps, dt_min_log2=-30, dt_max_log2=-3, precision=prec)
+    g.init()
+    g.predict(0.0)
+    for ipl, jl in SHAPES:  # every launch shape of the force kernel
+        for c in range(5):
+            g.set_tuning(ipl, jl, size_class=c)
+        acc, jerk, pot = g.force_jerk(il, 0.0)
+        ea = relerr(acc.T.cpu().numpy(), ra)
+        ej = relerr(jerk.T.cpu().numpy(), rj)
+        ep = relerr(pot.cpu().numpy(), rp)
+        note(f"  shape ({ipl}, {jl}) middle particle: FP32 pair terms {e32:.2e}, kernel "
+             f"{ea[101]:.2e}; max acc {ea.max():.2e}, jerk {ej.max():.2e}, pot {ep.max():.2e}")
+        assert ea.max() <= TOL[prec]["a"], (ipl, jl)
+        assert ej.max() <= TOL[prec]["j"], (ipl, jl)
+        assert ep.max() <= TOL[prec]["p"], (ipl, jl)
+    g.close()
+
+
 def test_unequal_masses_full_size_sweep_mixed():
     # N = 16384 Salpeter cluster, the start-up sweep on every particle
     note("salpeter N=16384 sweep")
