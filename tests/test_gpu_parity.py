@@ -3,7 +3,7 @@
 Tolerances (per particle, relative to the oracle's value):
   FP64 kernel:   acceleration <= 1e-11, jerk <= 1e-9 (different summation
                  order; the jerk sum cancels more), potential <= 1e-12;
-  mixed kernel:  acceleration <= 1e-6 (the spec bar), jerk <= 1e-5,
+  mixed kernel:  acceleration <= 1e-6 (the required accuracy), jerk <= 1e-5,
                  potential <= 1e-6.
 Block steps are compared state by state in FP64, where both sides take the
 same power-of-two decisions.
