@@ -136,7 +136,7 @@ const char *nbody_strerror(int status);
 /*
  * Create a context for the given parameters and caller-owned state.
  * `stream` is a hipStream_t (NULL = the null stream).  Allocates the
- * context's device buffers (about 120 B per particle plus the work plan).
+ * context's device buffers (about 140 B per particle plus the work plan).
  * The state is not read until nbody_init.
  * Errors: EINVAL (bad sizes, offsets, eps, eta, step range, precision or a
  * NULL state array), ENOMEM, EDEVICE.
@@ -180,6 +180,14 @@ int nbody_predict(nbody_ctx *ctx, double t);
  * arrays: acc_dev[c*n + k] is component c of particle i_list[k];
  * jerk_dev likewise; pot_dev[k] (pot_dev may be NULL).  1 <= n <= n_total.
  * Single-cluster contexts only.
+ *
+ * The mixed form evaluates in FP64 the pairs whose acceleration term may
+ * exceed a tenth of |a_i|, or whose jerk term may exceed twice |jerk_i|; it
+ * sizes that near field from the acceleration and jerk stored in the state
+ * for particle i, and from each cluster's largest and smallest mass and
+ * largest speed as nbody_init (or nbody_load) found them.  So the mixed form
+ * returns ESTATE before nbody_init or nbody_load, and masses must not change
+ * after nbody_init (call it again after changing them).
  */
 int nbody_force_jerk(nbody_ctx *ctx, const int32_t *i_list_dev, int64_t n, double t,
                      double *acc_dev, double *jerk_dev, double *pot_dev);
@@ -236,8 +244,9 @@ int nbody_run_until(nbody_ctx *ctx, double t_end, int64_t *n_steps_out);
  *
  * nbody_save synchronises, then writes to `path` (host file name): the
  * configuration (n_total, clusters and their offsets, eps, eta, eta_init, the
- * step range, precision), the statistics, the tuning table, and the particle
- * state (pos, vel, acc, jerk, mass as FP64; t_tick; level).  Little-endian
+ * step range, precision), the statistics, the tuning table, the mixed form's
+ * near-field scales of each cluster (set by nbody_init, see nbody_force_jerk),
+ * and the particle state (pos, vel, acc, jerk, mass as FP64; t_tick; level).  Little-endian
  * binary with a version and a 64-bit checksum; written to "<path>.part" and
  * renamed, so an existing file is only ever replaced by a complete one.
  * ESTATE before nbody_init; a pending device error is reported instead of

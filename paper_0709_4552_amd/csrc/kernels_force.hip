@@ -106,12 +106,23 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
     bool fused = false;
     auto fetch_m = [&](int64_t j, int64_t T, float4 &P, float4 &Q, float2 &R) {
         if (FUSE && fused) {
-            predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, j, T, P, Q, R);
+            float4 V;
+            predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, j, T, P, Q, R, V);
         } else {
             P = fa.jb.P[j];
             Q = fa.jb.Q[j];
             R = fa.jb.R[j];
         }
+    };
+    // low parts of particle j's FP32 velocity (the near field's FP64 velocities)
+    auto fetch_vlo = [&](int64_t j, int64_t T) -> float4 {
+        if (FUSE && fused) {
+            float4 P, Q, V;
+            float2 R;
+            predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, j, T, P, Q, R, V);
+            return V;
+        }
+        return fa.jb.V[j];
     };
     auto fetch_d = [&](int64_t j, int64_t T, double2 &A, double2 &B, double2 &C, double &D) {
         if (FUSE && fused) {
@@ -222,13 +233,34 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                 xh[ii] = p.x; yh[ii] = p.y; zh[ii] = p.z; mi[ii] = p.w;
                 xl[ii] = q.x; yl[ii] = q.y; zl[ii] = q.z; vxi[ii] = q.w;
                 vyi[ii] = r.x; vzi[ii] = r.y;
-                // near-field threshold on s from |a_i| (0 = none): per unit of
-                // m_j with PM, else for m_max
+                // near-field threshold on s from |a_i| and |jerk_i| (0 = none):
+                // per unit of m_j with PM, else for m_max
                 float sc = 0.f;
                 if (fa.near_frac > 0.f) {
+                    const float4 ns = fa.nscale[c];
                     const double ha = sqrt(fa.hax[i] * fa.hax[i] + fa.hay[i] * fa.hay[i] +
                                            fa.haz[i] * fa.haz[i]);
-                    const double v = (PM ? 1.0 : (double)fa.mmax[c]) / ((double)fa.near_frac * ha);
+                    double v = (PM ? 1.0 : (double)ns.x) / ((double)fa.near_frac * ha);
+                    if (fa.near_frac_jerk > 0.f) {
+                        // m V s^{-3/2} > f |jerk_i|  <=>  s < (m V / (f |jerk_i|))^{2/3};
+                        // with PM scaled per unit of m_j from the smallest mass,
+                        // which covers every heavier j with room to spare
+                        const double hj = sqrt(fa.hjx[i] * fa.hjx[i] + fa.hjy[i] * fa.hjy[i] +
+                                               fa.hjz[i] * fa.hjz[i]);
+                        const double V = sqrt((double)vxi[ii] * vxi[ii] + (double)vyi[ii] * vyi[ii] +
+                                              (double)vzi[ii] * vzi[ii]) + (double)ns.z;
+                        const double mref = PM ? (double)ns.y : (double)ns.x;
+                        const double q = mref * V / ((double)fa.near_frac_jerk * hj);
+                        // q^{2/3} from the hardware log2 / exp2 (a threshold needs
+                        // no more precision than that)
+                        const float qf = (float)fmin(q, 1.0e30);
+                        double sj = hj > 0.0 ? (double)__builtin_amdgcn_exp2f(
+                                                   __builtin_amdgcn_logf(qf) * (2.0f / 3.0f))
+                                             : 0.0;
+                        if (PM)
+                            sj /= mref;
+                        v = fmax(v, fmin(sj, 1.0e30));
+                    }
                     sc = (ha > 0.0 && v < 3.0e38) ? (float)v : 0.f;
                 }
                 scrit[ii] = sc;
@@ -423,10 +455,11 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                         }
                     }
                 }
-                // FP64 pass over the near pairs of this tile (double-single positions,
-                // FP64 masses, FP32 velocities)
+                // FP64 pass over the near pairs of this tile (double-single positions
+                // and velocities, FP64 masses)
 #pragma unroll
                 for (int ii = 0; ii < I; ii++) {
+                    #pragma unroll 1
                     for (int k = 0; k < ncnt[ii]; k++) {
                         const int t = sNear[(ii * kNearCap + k) * kWG + tid];
                         const int64_t j = tb + t;
@@ -446,9 +479,11 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                         const double ex = ((double)p.x - (double)xh[ii]) + ((double)q.x - (double)xl[ii]);
                         const double ey = ((double)p.y - (double)yh[ii]) + ((double)q.y - (double)yl[ii]);
                         const double ez = ((double)p.z - (double)zh[ii]) + ((double)q.z - (double)zl[ii]);
-                        const double ux = (double)(q.w - vxi[ii]);
-                        const double uy = (double)(r.x - vyi[ii]);
-                        const double uz = (double)(r.y - vzi[ii]);
+                        // velocity difference from the double-single velocities
+                        const float4 vlj = fetch_vlo(j, Tc), vli = fetch_vlo(gi[ii], Tc);
+                        const double ux = ((double)q.w - (double)vxi[ii]) + (double)(vlj.x - vli.x);
+                        const double uy = ((double)r.x - (double)vyi[ii]) + (double)(vlj.y - vli.y);
+                        const double uz = ((double)r.y - (double)vzi[ii]) + (double)(vlj.z - vli.z);
                         const double sd = fma(ez, ez, fma(ey, ey, fma(ex, ex, fa.eps2)));
                         const double ri = rsqrt_f64(sd);
                         const double ri2 = ri * ri;

@@ -53,12 +53,13 @@ template <int MIXED>
 __device__ inline void predict_one(const State &st, const Params &pr, const JBuf &jb, int64_t i,
                                    int64_t T) {
     if (MIXED) {
-        float4 P, Q;
+        float4 P, Q, V;
         float2 R;
-        predict_mixed(st, pr.tick, pr.grid_q, pr.grid_inv, i, T, P, Q, R);
+        predict_mixed(st, pr.tick, pr.grid_q, pr.grid_inv, i, T, P, Q, R, V);
         jb.P[i] = P;
         jb.Q[i] = Q;
         jb.R[i] = R;
+        jb.V[i] = V;
     } else {
         double2 A, B, C;
         double D;

@@ -50,7 +50,9 @@ struct nbody_ctx {
     double *part = nullptr;
     int64_t part_cap = 0;
     DevCtl *ctl = nullptr;
-    float *mmax_d = nullptr;  // [C] largest mass of each cluster
+    // [C] near-field scales of each cluster: largest mass, smallest mass,
+    // largest speed (the mixed form's FP64 near-field test), from init / load
+    float4 *nscale_d = nullptr;
 
     std::vector<void *> allocs;
 
@@ -174,9 +176,13 @@ ForceArgs force_args(nbody_ctx *c, const int32_t *i_list, int slots_at_offsets, 
     fa.hax = c->st.ax;
     fa.hay = c->st.ay;
     fa.haz = c->st.az;
+    fa.hjx = c->st.jx;
+    fa.hjy = c->st.jy;
+    fa.hjz = c->st.jz;
     fa.m64 = c->st.m;
-    fa.mmax = c->mmax_d;
+    fa.nscale = c->nscale_d;
     fa.near_frac = c->pr.precision == NBODY_PREC_MIXED ? kNearFrac : 0.f;
+    fa.near_frac_jerk = c->pr.precision == NBODY_PREC_MIXED ? kNearFracJerk : 0.f;
     fa.fused_mask = 0;
     fa.st = c->st;
     fa.t_cur = c->pl.t_cur;
@@ -315,37 +321,51 @@ hipError_t enqueue_block_step(nbody_ctx *c) {
 
 void drop_graph(nbody_ctx *c);
 
-// Largest |mass| of each cluster (the near-field threshold of the mixed form
-// uses it), and whether any cluster has unequal masses (then the mixed form
-// tests every pair with its own m_j), from a host copy of the masses.
-hipError_t upload_mass_max(nbody_ctx *c, const double *mh) {
-    std::vector<float> mx(c->pr.C, 0.f);
+// Near-field scales of each cluster from host copies of the masses and the
+// velocities (vel[q*N + i]): the largest and smallest |mass| and the largest
+// speed, which bound a pair's acceleration and jerk terms in the mixed
+// form's near-field test; and whether any cluster has unequal masses (then
+// the mixed form tests every pair with its own m_j).
+hipError_t upload_cluster_scales(nbody_ctx *c, const double *mh, const double *vh,
+                                 const float4 *saved = nullptr) {
+    const int64_t N = c->pr.n_total;
+    std::vector<float4> sc(c->pr.C);
     bool unequal = false;
     for (int k = 0; k < c->pr.C; k++) {
-        double v = 0.0;
+        double mx = 0.0, mn = INFINITY, vmax = 0.0;
         const double m0 = mh[c->off_h[k]];
         for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++) {
-            v = std::max(v, std::fabs(mh[i]));
+            const double a = std::fabs(mh[i]);
+            mx = std::max(mx, a);
+            mn = std::min(mn, a);
             unequal = unequal || mh[i] != m0;
+            const double v2 = vh[i] * vh[i] + vh[N + i] * vh[N + i] + vh[2 * N + i] * vh[2 * N + i];
+            vmax = std::max(vmax, std::sqrt(v2));
         }
-        mx[k] = (float)v;
+        sc[k] = make_float4((float)mx, (float)mn, std::isfinite(vmax) ? (float)vmax : 0.f, 0.f);
     }
+    // a resumed run keeps the scales its start-up set (the speeds at the
+    // checkpoint differ), so it takes the same near-field decisions
+    if (saved)
+        for (int k = 0; k < c->pr.C; k++)
+            sc[k] = saved[k];
     const int pm = (c->pr.precision == NBODY_PREC_MIXED && unequal) ? 1 : 0;
     if (pm != c->pair_mass) {
         c->pair_mass = pm;
         std::memset(c->occ_cache, 0, sizeof(c->occ_cache));
         drop_graph(c);
     }
-    return hipMemcpy(c->mmax_d, mx.data(), mx.size() * sizeof(float), hipMemcpyHostToDevice);
+    return hipMemcpy(c->nscale_d, sc.data(), sc.size() * sizeof(float4), hipMemcpyHostToDevice);
 }
 
 // ---- checkpoint file ----
 // Little-endian binary: magic, version, the context's configuration (checked on
-// load), statistics, tuning table, then the particle state as 13 FP64 arrays
-// (x y z vx vy vz ax ay az jx jy jz m), int64 ticks and int8 levels, and an
-// FNV-1a 64-bit checksum of everything after the magic.
+// load), statistics, tuning table, the near-field scales of each cluster (4
+// floats), then the particle state as 13 FP64 arrays (x y z vx vy vz ax ay az
+// jx jy jz m), int64 ticks and int8 levels, and an FNV-1a 64-bit checksum of
+// everything after the magic.
 constexpr char kCkptMagic[8] = {'N', 'B', 'O', 'D', 'Y', 'C', 'K', 'P'};
-constexpr uint32_t kCkptVersion = 1;
+constexpr uint32_t kCkptVersion = 2;
 
 struct Fnv {
     uint64_t h = 1469598103934665603ull;
@@ -592,11 +612,11 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
         (e = dalloc(c, &c->jerk_new, 3 * N)) != hipSuccess ||
         (e = dalloc(c, &c->pot_new, N)) != hipSuccess ||
         (e = dalloc(c, &c->part, 7 * c->part_cap)) != hipSuccess ||
-        (e = dalloc(c, &c->ctl, 1)) != hipSuccess || (e = dalloc(c, &c->mmax_d, C)) != hipSuccess)
+        (e = dalloc(c, &c->ctl, 1)) != hipSuccess || (e = dalloc(c, &c->nscale_d, C)) != hipSuccess)
         return fail(e);
     if (mixed) {
         if ((e = dalloc(c, &c->jb.P, N)) != hipSuccess || (e = dalloc(c, &c->jb.Q, N)) != hipSuccess ||
-            (e = dalloc(c, &c->jb.R, N)) != hipSuccess)
+            (e = dalloc(c, &c->jb.R, N)) != hipSuccess || (e = dalloc(c, &c->jb.V, N)) != hipSuccess)
             return fail(e);
     } else {
         if ((e = dalloc(c, &c->jb.A, N)) != hipSuccess || (e = dalloc(c, &c->jb.B, N)) != hipSuccess ||
@@ -612,6 +632,13 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
     h.t_end_tick = LLONG_MAX;
     if ((e = hipMemcpy(c->ctl, &h, sizeof(h), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
+    {
+        // no near-field scales until init / load (the mixed force refuses to
+        // run before either)
+        const std::vector<float4> zero(C, make_float4(0.f, 0.f, 0.f, 0.f));
+        if ((e = hipMemcpy(c->nscale_d, zero.data(), C * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess)
+            return fail(e);
+    }
     if ((e = launch_iota_i32(c->iota_d, N, c->stream)) != hipSuccess ||
         (e = launch_fill_i32(c->i_list_d, 0, N, c->stream)) != hipSuccess ||
         (e = launch_fill_i32(c->n_act_d, 0, C, c->stream)) != hipSuccess ||
@@ -660,10 +687,13 @@ int nbody_init(nbody_ctx *c) {
     for (int k = 0; k < c->pr.C; k++)
         nc[k] = (int32_t)(c->off_h[k + 1] - c->off_h[k]);
     {
-        std::vector<double> mh(N);
+        std::vector<double> mh(N), vh(3 * N);
         NB_TRY(hipStreamSynchronize(c->stream));
         NB_TRY(hipMemcpy(mh.data(), c->st.m, N * sizeof(double), hipMemcpyDeviceToHost));
-        NB_TRY(upload_mass_max(c, mh.data()));
+        const double *vs[3] = {c->st.vx, c->st.vy, c->st.vz};
+        for (int q = 0; q < 3; q++)
+            NB_TRY(hipMemcpy(vh.data() + q * N, vs[q], N * sizeof(double), hipMemcpyDeviceToHost));
+        NB_TRY(upload_cluster_scales(c, mh.data(), vh.data()));
     }
     // mixed: a first sweep without near field gives |a| for the thresholds
     const int passes = c->pr.precision == NBODY_PREC_MIXED ? 2 : 1;
@@ -713,6 +743,10 @@ int nbody_force_jerk(nbody_ctx *c, const int32_t *i_list, int64_t n, double t, d
     if (!is_multiple_tick(t, c->pr.dt_min_log2, &tick))
         return NBODY_EINVAL;
     if (!c->predicted || c->predicted_tick != tick)
+        return NBODY_ESTATE;
+    // the mixed form's near-field test needs the scales and the stored
+    // acceleration and jerk that nbody_init / nbody_load provide
+    if (c->pr.precision == NBODY_PREC_MIXED && !c->initialised)
         return NBODY_ESTATE;
     NB_TRY(enqueue_force(c, i_list, 0, (int32_t)n, tick, 0, acc, jerk, pot, n, n));
     return NBODY_OK;
@@ -889,6 +923,9 @@ int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *be
         sum += nc[k];
     }
     const int cls = class_of(c, sum / c->pr.C);
+    // the time the j-particle buffer was predicted to, where known (the near
+    // field's FP64 velocities are predicted to the evaluation time)
+    const int64_t t_probe = c->predicted ? c->predicted_tick : 0;
     static const Shape cand[] = {{1, 1, 256}, {2, 1, 256}, {1, 4, 256}, {1, 16, 256},
                                  {1, 64, 256}, {1, 256, 256}};
     const Shape keep = c->cls_shape[cls];
@@ -910,13 +947,13 @@ int nbody_autotune(nbody_ctx *c, int64_t n_probe, nbody_tuning *best, double *be
             if (c->pr.C == 1) {
                 e = hipEventRecord(e0, c->stream);
                 if (e == hipSuccess)
-                    e = enqueue_force(c, c->iota_d, 0, nc[0], 0, 0, c->acc_new, c->jerk_new,
-                                      nullptr, N, nc[0]);
+                    e = enqueue_force(c, c->iota_d, 0, nc[0], t_probe, 0, c->acc_new,
+                                      c->jerk_new, nullptr, N, nc[0]);
             } else {
                 e = hipMemcpyAsync(c->n_act_d, nc.data(), nc.size() * sizeof(int32_t),
                                    hipMemcpyHostToDevice, c->stream);
                 if (e == hipSuccess)
-                    e = launch_fill_i64(c->t_next_d, 0, c->pr.C, c->stream);
+                    e = launch_fill_i64(c->t_next_d, t_probe, c->pr.C, c->stream);
                 if (e == hipSuccess)
                     e = hipEventRecord(e0, c->stream);
                 if (e == hipSuccess)
@@ -1023,6 +1060,9 @@ int nbody_save(nbody_ctx *c, const char *path) {
         NB_TRY(hipMemcpy(buf.data() + q * N, src[q], N * sizeof(double), hipMemcpyDeviceToHost));
     NB_TRY(hipMemcpy(tick.data(), st.tick, N * sizeof(int64_t), hipMemcpyDeviceToHost));
     NB_TRY(hipMemcpy(lev.data(), st.lev, N * sizeof(int8_t), hipMemcpyDeviceToHost));
+    std::vector<float4> scales(c->pr.C);
+    NB_TRY(hipMemcpy(scales.data(), c->nscale_d, scales.size() * sizeof(float4),
+                     hipMemcpyDeviceToHost));
 
     // write beside the target, then rename: an existing checkpoint is replaced
     // only by a complete one
@@ -1052,6 +1092,7 @@ int nbody_save(nbody_ctx *c, const char *path) {
                               c->cls_shape[q].j_tile, c->cls_grid[q]};
         w.put(t, sizeof(t));
     }
+    w.put(scales.data(), scales.size() * sizeof(float4));
     w.put(buf.data(), buf.size() * sizeof(double));
     w.put(tick.data(), tick.size() * sizeof(int64_t));
     w.put(lev.data(), lev.size());
@@ -1128,13 +1169,16 @@ int nbody_load(nbody_ctx *c, const char *path) {
     std::vector<double> buf;
     std::vector<int64_t> tick;
     std::vector<int8_t> lev;
+    std::vector<float4> scales;
     try {
         buf.resize(13 * (size_t)N);
         tick.resize(N);
         lev.resize(N);
+        scales.resize(c->pr.C);
     } catch (const std::bad_alloc &) {
         return done(NBODY_ENOMEM);
     }
+    r.get(scales.data(), scales.size() * sizeof(float4));
     r.get(buf.data(), buf.size() * sizeof(double));
     r.get(tick.data(), tick.size() * sizeof(int64_t));
     r.get(lev.data(), lev.size());
@@ -1156,7 +1200,7 @@ int nbody_load(nbody_ctx *c, const char *path) {
         NB_TRY(hipMemcpy(dst[q], buf.data() + q * N, N * sizeof(double), hipMemcpyHostToDevice));
     NB_TRY(hipMemcpy(st.tick, tick.data(), N * sizeof(int64_t), hipMemcpyHostToDevice));
     NB_TRY(hipMemcpy(st.lev, lev.data(), N * sizeof(int8_t), hipMemcpyHostToDevice));
-    NB_TRY(upload_mass_max(c, buf.data() + 12 * N));
+    NB_TRY(upload_cluster_scales(c, buf.data() + 12 * N, buf.data() + 3 * N, scales.data()));
     DevCtl h;
     int rc = read_ctl(c, &h);
     if (rc != NBODY_OK)

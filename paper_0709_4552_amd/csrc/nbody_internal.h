@@ -69,12 +69,14 @@ struct ClassTable {
 // Predicted j-particle buffer.
 //  mixed: P = (x_hi, y_hi, z_hi, m), Q = (x_lo, y_lo, z_lo, vx), R = (vy, vz)
 //         with x_hi = q rint(x/q) on the fixed grid q (so x_hi_j - x_hi_i is
-//         exact in FP32) and x_lo = fl32(x - x_hi)
+//         exact in FP32) and x_lo = fl32(x - x_hi); V = (vx_lo, vy_lo, vz_lo, 0)
+//         with v_lo = fl32(v - fl32(v)), read only by the FP64 near field
 //  fp64 : A = (x, y), B = (z, m), C = (vx, vy), D = vz
 struct JBuf {
     float4 *P = nullptr;
     float4 *Q = nullptr;
     float2 *R = nullptr;
+    float4 *V = nullptr;
     double2 *A = nullptr;
     double2 *B = nullptr;
     double2 *C = nullptr;
@@ -114,10 +116,16 @@ struct Params {
     double grid_inv;                // 1 / grid_q
 };
 
-// Mixed precision near field: a pair whose term may exceed kNearFrac*|a_i|
-// (m_max/s > kNearFrac*|a_i|, with |a_i| the particle's last acceleration) is
-// evaluated in FP64 instead of FP32.
+// Mixed precision near field: a pair whose acceleration term may exceed
+// kNearFrac*|a_i| (m_max/s > kNearFrac*|a_i|, with |a_i| the particle's last
+// acceleration), or whose jerk term may exceed kNearFracJerk*|jerk_i|
+// (m_max V_i s^{-3/2} > kNearFracJerk*|jerk_i|, with V_i = |v_i| + v_max the
+// largest relative speed the cluster allows and |jerk_i| the particle's last
+// jerk) is evaluated in FP64 instead of FP32.  The jerk sum cancels more than
+// the acceleration sum: a pair term tens of times the total is common, and
+// its FP32 rounding alone then costs ~1e-5 of the particle's jerk.
 constexpr float kNearFrac = 0.1f;
+constexpr float kNearFracJerk = 2.0f;
 constexpr int kGridQLog2 = -16;  // hi parts on a 2^-16 grid: exact differences for |x| < 256
 
 // Everything the force kernels need.
@@ -152,9 +160,11 @@ struct ForceArgs {
     float eps2f;
     // mixed near field
     const double *hax, *hay, *haz;  // |a_i| hint: the particle's stored acceleration
+    const double *hjx, *hjy, *hjz;  // |jerk_i| hint: the particle's stored jerk
     const double *m64;              // FP64 masses
-    const float *mmax;              // [C] largest mass of each cluster
+    const float4 *nscale;           // [C] (largest mass, smallest mass, largest speed, 0)
     float near_frac;                // 0 disables the near field
+    float near_frac_jerk;           // 0 disables its jerk criterion
     uint32_t cls_lj;                // lane-group launches: log2(j lanes) of class k
                                     // in bits 4k..4k+3
     // in-kernel prediction (lane-group launches, one cluster): classes in
@@ -188,19 +198,30 @@ __device__ inline void predict_terms(const State &st, double tick, int64_t i, in
     vzp = fma(d, fma(h, jz, az), vz);
 }
 
-__device__ inline void predict_mixed(const State &st, double tick, double grid_q, double grid_inv,
-                                     int64_t i, int64_t T, float4 &P, float4 &Q, float2 &R) {
-    double xp, yp, zp, vxp, vyp, vzp;
-    predict_terms(st, tick, i, T, xp, yp, zp, vxp, vyp, vzp);
+// The mixed j-record of a particle at (xp, vp) with mass m.
+__device__ inline void split_mixed(double xp, double yp, double zp, double vxp, double vyp,
+                                   double vzp, double m, double grid_q, double grid_inv,
+                                   float4 &P, float4 &Q, float2 &R, float4 &V) {
     // hi on a fixed grid: differences of hi parts are exact, so the rounding
     // of x_j - x_i does not depend on i's low bits
     const float xh = (float)(rint(xp * grid_inv) * grid_q);
     const float yh = (float)(rint(yp * grid_inv) * grid_q);
     const float zh = (float)(rint(zp * grid_inv) * grid_q);
-    P = make_float4(xh, yh, zh, (float)st.m[i]);
+    P = make_float4(xh, yh, zh, (float)m);
     Q = make_float4((float)(xp - (double)xh), (float)(yp - (double)yh),
                     (float)(zp - (double)zh), (float)vxp);
     R = make_float2((float)vyp, (float)vzp);
+    // what FP32 velocities drop: v = fl32(v) + v_lo to ~2^-48 |v|
+    V = make_float4((float)(vxp - (double)Q.w), (float)(vyp - (double)R.x),
+                    (float)(vzp - (double)R.y), 0.f);
+}
+
+__device__ inline void predict_mixed(const State &st, double tick, double grid_q, double grid_inv,
+                                     int64_t i, int64_t T, float4 &P, float4 &Q, float2 &R,
+                                     float4 &V) {
+    double xp, yp, zp, vxp, vyp, vzp;
+    predict_terms(st, tick, i, T, xp, yp, zp, vxp, vyp, vzp);
+    split_mixed(xp, yp, zp, vxp, vyp, vzp, st.m[i], grid_q, grid_inv, P, Q, R, V);
 }
 
 __device__ inline void predict_fp64(const State &st, double tick, int64_t i, int64_t T,

@@ -278,6 +278,96 @@ def test_near_pairs_are_evaluated_in_fp64(prec):
     g.close()
 
 
+def fp32_pair_terms_jerk(x, v, m, eps, i, q=2.0 ** -16):
+    """Jerk on i with every pair term in FP32 (double-single position
+    differences as the mixed kernel forms them, FP32 velocities), the terms
+    summed in FP64: the mixed form without its FP64 near field."""
+    hi = np.rint(x / q) * q
+    lo = (x - hi).astype(np.float32)
+    hi = hi.astype(np.float32)
+    d = ((hi - hi[i]) + (lo - lo[i])).astype(np.float32)
+    v32 = v.astype(np.float32)
+    w = (v32 - v32[i]).astype(np.float32)
+    s = (d * d).sum(axis=1, dtype=np.float32) + np.float32(eps * eps)
+    rinv = (np.float32(1) / np.sqrt(s)).astype(np.float32)
+    mr3 = (m.astype(np.float32) * rinv * rinv * rinv).astype(np.float32)
+    rw = (d * w).sum(axis=1, dtype=np.float32)
+    be = (mr3 * rw * rinv * rinv).astype(np.float32)
+    f = (mr3[:, None] * w - np.float32(3) * be[:, None] * d).astype(np.float64)
+    f[i] = 0.0
+    return f.sum(axis=0)
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_jerk_near_pairs_are_evaluated_in_fp64(prec):
+    # Particle 0 at rest between two particles 0.2 away on either side that
+    # move past it in opposite directions at nearly the same speed: their jerk
+    # terms (~125 m each) cancel to 1e-3 of that, and a clump of 1000
+    # particles at rest at distance 1 gives it |a| ~ 1 and no jerk.  The two
+    # force terms (25 m) stay under the near-field share of |a|, so only the
+    # jerk criterion sends these pairs to FP64; FP32 pair terms miss the jerk
+    # by ~1e-4 (checked below on the CPU).  All masses are equal.
+    note(f"jerk near pairs in FP64 prec={prec}")
+    rng = np.random.Generator(np.random.PCG64(1019))
+    N = 1003
+    x = np.zeros((N, 3))
+    v = np.zeros((N, 3))
+    x[1] = (0.2, 0.0, 0.0)
+    v[1] = (0.0, -1.0, 0.0)
+    x[2] = (-0.2, 0.0, 0.0)
+    v[2] = (0.0, 1.0 + 1e-3, 0.0)
+    x[3:] = (0.0, 0.0, 1.0) + 0.01 * rng.uniform(-1.0, 1.0, (N - 3, 3))
+    m = np.full(N, 1.0 / N)
+    eps = 1e-3
+    il = np.arange(N, dtype=np.int32)
+    ra, rj, rp = oracle.force(x, v, m, eps, il)
+    e32 = relerr(fp32_pair_terms_jerk(x, v, m, eps, 0)[None, :], rj[0][None, :])[0]
+    assert e32 > 1e-5  # the configuration defeats FP32 pair terms
+    g = NBody(x, v, m, eps, dt_min_log2=-30, dt_max_log2=-3, precision=prec)
+    g.init()
+    g.predict(0.0)
+    for ipl, jl in SHAPES:  # every launch shape of the force kernel
+        for c in range(5):
+            g.set_tuning(ipl, jl, size_class=c)
+        acc, jerk, pot = g.force_jerk(il, 0.0)
+        ea = relerr(acc.T.cpu().numpy(), ra)
+        ej = relerr(jerk.T.cpu().numpy(), rj)
+        ep = relerr(pot.cpu().numpy(), rp)
+        note(f"  shape ({ipl}, {jl}) particle 0: FP32 pair terms {e32:.2e}, kernel jerk "
+             f"{ej[0]:.2e}; max acc {ea.max():.2e}, jerk {ej.max():.2e}, pot {ep.max():.2e}")
+        assert ea.max() <= TOL[prec]["a"], (ipl, jl)
+        assert ej.max() <= TOL[prec]["j"], (ipl, jl)
+        assert ep.max() <= TOL[prec]["p"], (ipl, jl)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_force_before_init(prec):
+    # The mixed form's near field needs what nbody_init (or nbody_load) sets:
+    # the stored acceleration and jerk and the cluster's mass and speed
+    # scales.  Before either, its force call is refused; the FP64 form needs
+    # none of it.
+    note(f"force before init prec={prec}")
+    N = 300
+    x, v, m = plummer(N, 1008)
+    eps = 1 / 256
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    il = np.arange(N, dtype=np.int32)
+    g.predict(0.0)
+    if prec == NBODY_PREC_MIXED:
+        with pytest.raises(NBodyError) as e:
+            g.force_jerk(il, 0.0)
+        assert e.value.code == _lib.NBODY_ESTATE
+        g.init()
+        g.predict(0.0)
+    acc, jerk, pot = g.force_jerk(il, 0.0)
+    ra, rj, rp = oracle.force(x, v, m, eps, il)
+    assert relerr(acc.T.cpu().numpy(), ra).max() <= TOL[prec]["a"]
+    assert relerr(jerk.T.cpu().numpy(), rj).max() <= TOL[prec]["j"]
+    assert relerr(pot.cpu().numpy(), rp).max() <= TOL[prec]["p"]
+    g.close()
+
+
 def test_unequal_masses_full_size_sweep_mixed():
     # N = 16384 Salpeter cluster, the start-up sweep on every particle
     note("salpeter N=16384 sweep")
