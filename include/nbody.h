@@ -59,6 +59,7 @@ extern "C" {
 #define NBODY_EUNSUPPORTED (-6) /* valid but not supported by this library       */
 #define NBODY_ERANGE (-7)       /* the device met a particle index out of range  */
 #define NBODY_EIO (-8)          /* checkpoint file not writable / readable / valid */
+#define NBODY_ESCRATCH (-9)     /* more particles than nbody_force_jerk_static holds */
 
 /* arithmetic of the pairwise force sum */
 #define NBODY_PREC_FP64 0  /* every operation in FP64                             */
@@ -313,6 +314,52 @@ int nbody_set_fused_predict(nbody_ctx *ctx, int32_t class_mask);
  * *best_ms (may be NULL) its time for one force evaluation in milliseconds.
  */
 int nbody_autotune(nbody_ctx *ctx, int64_t n_probe, nbody_tuning *best, double *best_ms);
+
+/*
+ * Allocation-free force evaluation, for callers that cannot allocate device
+ * memory: code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  It computes what nbody_force_jerk computes (the same
+ * kernels and arithmetic, both precisions) without a context: on the n
+ * listed particles, from all n_j particles given, at the positions and
+ * velocities given (no prediction; the evaluation time is the particles').
+ * The buffers its kernels need beyond the inputs and outputs (the j-particle
+ * records, near-field hints, partial sums of split j ranges, the work plan
+ * and counters) live in one statically sized device array of the library,
+ * about 35 MB on each GPU it runs on, held until the process ends; the call
+ * allocates nothing, sets no memory with hipMemset and does not synchronise.
+ *
+ * in: host struct of device pointers (SoA FP64, n_j entries each).  In the
+ *   mixed form the near field is sized as in nbody_force_jerk, from
+ *   acc_hint/jerk_hint (the particles' acceleration and jerk at or shortly
+ *   before this time, e.g. from the previous evaluation; all six NULL: a first
+ *   pass without the near field supplies them, doubling the work), and the
+ *   masses are always tested pair by pair.  The FP64 form ignores the hints.
+ * i_list_dev, n, acc_dev, jerk_dev, pot_dev: as in nbody_force_jerk
+ *   (pot_dev may be NULL); an index outside [0, n_j) leaves that slot's
+ *   outputs unspecified (it is not reported: there is no context).
+ * stream: hipStream_t (NULL = the null stream).  Asynchronous.
+ *
+ * Errors (host-checked, nothing enqueued): EINVAL for NULL pointers, bad eps
+ * or precision, n or n_j below 1, or only some hint arrays given; ESCRATCH
+ * for n_j or n above NBODY_STATIC_MAX_PARTICLES (2^18, also the j-memory
+ * size of the GRAPE-6Af boards of the paper, section 5); EDEVICE on a HIP
+ * error.  All calls on one GPU share the array: calls that overlap on one GPU
+ * (other streams, other threads) race and must be serialised by the caller.
+ */
+#define NBODY_STATIC_MAX_PARTICLES 262144
+typedef struct {
+    int64_t n_j;                 /* particles, 1..NBODY_STATIC_MAX_PARTICLES  */
+    const double *pos[3];        /* x, y, z                                   */
+    const double *vel[3];        /* vx, vy, vz                                */
+    const double *mass;          /* m                                         */
+    const double *acc_hint[3];   /* mixed: |a| hints by particle, or NULL     */
+    const double *jerk_hint[3];  /* mixed: |jerk| hints by particle, or NULL  */
+    double eps;                  /* softening length, >= 0                    */
+    int32_t precision;           /* NBODY_PREC_FP64 or NBODY_PREC_MIXED       */
+} nbody_direct;
+
+int nbody_force_jerk_static(const nbody_direct *in, const int32_t *i_list_dev, int64_t n,
+                            double *acc_dev, double *jerk_dev, double *pot_dev, void *stream);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,8 @@ from . import _lib
 from ._lib import (NBODY_PREC_FP64, NBODY_PREC_MIXED, NBodyError, check,  # noqa: F401
                    nbody_tuning)
 
-__all__ = ["NBody", "NBodyError", "NBODY_PREC_FP64", "NBODY_PREC_MIXED", "nbody_tuning"]
+__all__ = ["NBody", "NBodyError", "NBODY_PREC_FP64", "NBODY_PREC_MIXED", "nbody_tuning",
+           "force_jerk_static"]
 
 
 def _torch():
@@ -192,3 +193,38 @@ class NBody:
         t = self.t_tick.cpu().numpy().astype(np.float64) * 2.0 ** self.dt_min_log2
         dt = 2.0 ** (-self.level.cpu().numpy().astype(np.float64))
         return x, v, a, j, t, dt
+
+
+def force_jerk_static(pos, vel, mass, eps: float, i_list, precision: int = NBODY_PREC_MIXED,
+                      acc_hint=None, jerk_hint=None, want_pot: bool = True, stream=None):
+    """Force, jerk and potential on the particles i_list from all particles
+    given, through the allocation-free entry point (nbody_force_jerk_static).
+
+    pos, vel: float64 device tensors (3, n_j), contiguous rows; mass: (n_j,);
+    acc_hint, jerk_hint: (3, n_j) or None (mixed form only).  Returns
+    (acc (3, n), jerk (3, n), pot (n,) or None) as device tensors, allocated
+    here by torch (the library call itself allocates nothing).
+    """
+    torch = _torch()
+    dev = pos.device
+    il = torch.as_tensor(i_list, dtype=torch.int32, device=dev).contiguous()
+    n = il.numel()
+    d = _lib.nbody_direct()
+    d.n_j = int(mass.numel())
+    for c in range(3):
+        d.pos[c] = pos[c].data_ptr()
+        d.vel[c] = vel[c].data_ptr()
+        d.acc_hint[c] = acc_hint[c].data_ptr() if acc_hint is not None else None
+        d.jerk_hint[c] = jerk_hint[c].data_ptr() if jerk_hint is not None else None
+    d.mass = mass.data_ptr()
+    d.eps = float(eps)
+    d.precision = int(precision)
+    acc = torch.empty((3, n), dtype=torch.float64, device=dev)
+    jerk = torch.empty((3, n), dtype=torch.float64, device=dev)
+    pot = torch.empty(n, dtype=torch.float64, device=dev) if want_pot else None
+    s = stream if stream is not None else torch.cuda.current_stream(dev)
+    check(_lib.nbody_force_jerk_static(d, il.data_ptr(), n, acc.data_ptr(), jerk.data_ptr(),
+                                       pot.data_ptr() if want_pot else None, s.cuda_stream),
+          "nbody_force_jerk_static")
+    s.synchronize()  # il must outlive the asynchronous call
+    return acc, jerk, pot

@@ -21,6 +21,8 @@ NBODY_ENONFINITE = -5
 NBODY_EUNSUPPORTED = -6
 NBODY_ERANGE = -7
 NBODY_EIO = -8
+NBODY_ESCRATCH = -9
+NBODY_STATIC_MAX_PARTICLES = 262144
 
 NBODY_PREC_FP64 = 0
 NBODY_PREC_MIXED = 1
@@ -31,6 +33,7 @@ EXPORTS = (
     "nbody_force_jerk", "nbody_correct", "nbody_step_block", "nbody_run_until", "nbody_sync",
     "nbody_get_stats", "nbody_read_predicted", "nbody_get_tuning", "nbody_set_tuning",
     "nbody_autotune", "nbody_save", "nbody_load", "nbody_set_fused_predict",
+    "nbody_force_jerk_static",
 )
 
 
@@ -70,6 +73,19 @@ class nbody_tuning(ctypes.Structure):
         ("j_lanes", ctypes.c_int32),
         ("j_tile", ctypes.c_int32),
         ("grid", ctypes.c_int32),
+    ]
+
+
+class nbody_direct(ctypes.Structure):
+    _fields_ = [
+        ("n_j", ctypes.c_int64),
+        ("pos", ctypes.c_void_p * 3),
+        ("vel", ctypes.c_void_p * 3),
+        ("mass", ctypes.c_void_p),
+        ("acc_hint", ctypes.c_void_p * 3),
+        ("jerk_hint", ctypes.c_void_p * 3),
+        ("eps", ctypes.c_double),
+        ("precision", ctypes.c_int32),
     ]
 
 
@@ -119,6 +135,7 @@ def load(path: str = LIB_PATH):
     L.nbody_set_tuning.argtypes = [vp, ctypes.POINTER(nbody_tuning)]
     L.nbody_set_fused_predict.argtypes = [vp, ctypes.c_int32]
     L.nbody_autotune.argtypes = [vp, i64, ctypes.POINTER(nbody_tuning), ctypes.POINTER(d)]
+    L.nbody_force_jerk_static.argtypes = [ctypes.POINTER(nbody_direct), vp, i64, vp, vp, vp, vp]
     L.nbody_save.argtypes = [vp, ctypes.c_char_p]
     L.nbody_load.argtypes = [vp, ctypes.c_char_p]
     for name in EXPORTS:
@@ -231,3 +248,11 @@ def nbody_save(ctx: int, path: str) -> int:
 
 def nbody_load(ctx: int, path: str) -> int:
     return load().nbody_load(ctypes.c_void_p(ctx), os.fsencode(path))
+
+
+def nbody_force_jerk_static(direct: nbody_direct, i_list_ptr: int, n: int, acc_ptr: int,
+                            jerk_ptr: int, pot_ptr: int | None, stream: int | None) -> int:
+    return load().nbody_force_jerk_static(ctypes.byref(direct), ctypes.c_void_p(i_list_ptr),
+                                          int(n), ctypes.c_void_p(acc_ptr),
+                                          ctypes.c_void_p(jerk_ptr), ctypes.c_void_p(pot_ptr or 0),
+                                          ctypes.c_void_p(stream or 0))

@@ -254,7 +254,7 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                         // q^{2/3} from the hardware log2 / exp2 (a threshold needs
                         // no more precision than that)
                         const float qf = (float)fmin(q, 1.0e30);
-                        double sj = hj > 0.0 ? (double)__builtin_amdgcn_exp2f(
+                        double sj = (hj > 0.0 && mref > 0.0) ? (double)__builtin_amdgcn_exp2f(
                                                    __builtin_amdgcn_logf(qf) * (2.0f / 3.0f))
                                              : 0.0;
                         if (PM)

@@ -337,12 +337,14 @@ hipError_t upload_cluster_scales(nbody_ctx *c, const double *mh, const double *v
         for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++) {
             const double a = std::fabs(mh[i]);
             mx = std::max(mx, a);
-            mn = std::min(mn, a);
+            if (a > 0.0)  // the smallest mass that attracts
+                mn = std::min(mn, a);
             unequal = unequal || mh[i] != m0;
             const double v2 = vh[i] * vh[i] + vh[N + i] * vh[N + i] + vh[2 * N + i] * vh[2 * N + i];
             vmax = std::max(vmax, std::sqrt(v2));
         }
-        sc[k] = make_float4((float)mx, (float)mn, std::isfinite(vmax) ? (float)vmax : 0.f, 0.f);
+        sc[k] = make_float4((float)mx, std::isfinite(mn) ? (float)mn : 0.f,
+                            std::isfinite(vmax) ? (float)vmax : 0.f, 0.f);
     }
     // a resumed run keeps the scales its start-up set (the speeds at the
     // checkpoint differ), so it takes the same near-field decisions
@@ -479,6 +481,7 @@ const char *nbody_strerror(int status) {
         case NBODY_EUNSUPPORTED: return "unsupported";
         case NBODY_ERANGE: return "particle index out of range";
         case NBODY_EIO: return "checkpoint file could not be written or read, or is damaged";
+        case NBODY_ESCRATCH: return "more particles than the allocation-free evaluation holds";
         default: return "unknown status";
     }
 }

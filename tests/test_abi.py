@@ -35,10 +35,12 @@ def test_struct_layouts_match_header():
     assert ctypes.sizeof(_lib.nbody_params) == 8 + 8 + 8 + 24 + 16
     assert ctypes.sizeof(_lib.nbody_tuning) == 20
     assert ctypes.sizeof(_lib.nbody_stats) == 32
+    # nbody_direct: int64, 13 pointers, double, int32 (+pad)
+    assert ctypes.sizeof(_lib.nbody_direct) == 8 + 13 * 8 + 8 + 8
 
 
 def test_strerror_names_every_code():
-    for code in range(0, -9, -1):
+    for code in range(0, -10, -1):
         assert _lib.strerror(code) != "unknown status"
     assert _lib.strerror(-99) == "unknown status"
 
@@ -111,3 +113,37 @@ def test_null_context_is_rejected():
     assert L.nbody_save(None, b"/tmp/x") == _lib.NBODY_EINVAL
     assert L.nbody_load(None, b"/tmp/x") == _lib.NBODY_EINVAL
     assert L.nbody_set_fused_predict(None, 0) == _lib.NBODY_EINVAL
+
+
+def _direct(**kw):
+    d = _lib.nbody_direct()
+    fake = 0x1000  # never dereferenced: the call fails on the host checks first
+    d.n_j = kw.get("n_j", 16)
+    for c in range(3):
+        d.pos[c] = d.vel[c] = fake
+    d.mass = fake
+    for c in kw.get("hints", ()):
+        d.acc_hint[c] = fake
+    d.eps = kw.get("eps", 0.01)
+    d.precision = kw.get("precision", 1)
+    if kw.get("null_mass"):
+        d.mass = None
+    return d
+
+
+@pytest.mark.parametrize("kw,n,code", [
+    (dict(n_j=_lib.NBODY_STATIC_MAX_PARTICLES + 1), 1, _lib.NBODY_ESCRATCH),
+    (dict(n_j=16), _lib.NBODY_STATIC_MAX_PARTICLES + 1, _lib.NBODY_ESCRATCH),
+    (dict(n_j=0), 1, _lib.NBODY_EINVAL),
+    (dict(n_j=16), 0, _lib.NBODY_EINVAL),
+    (dict(eps=-1.0), 1, _lib.NBODY_EINVAL),
+    (dict(precision=3), 1, _lib.NBODY_EINVAL),
+    (dict(null_mass=True), 1, _lib.NBODY_EINVAL),
+    (dict(hints=(0, 1, 2)), 1, _lib.NBODY_EINVAL),  # acceleration hints without jerk hints
+])
+def test_static_force_rejects_bad_arguments(kw, n, code):
+    # checked on the host before any device call (no GPU is touched here)
+    L = _lib.load()
+    out = ctypes.c_void_p(0x1000)
+    rc = L.nbody_force_jerk_static(ctypes.byref(_direct(**kw)), out, n, out, out, None, None)
+    assert rc == code
