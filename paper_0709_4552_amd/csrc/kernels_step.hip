@@ -1019,6 +1019,15 @@ __global__ __launch_bounds__(kWG) void k_init_finish(State st, Params pr, const 
         atomicAdd(&ctl->clamps, clamps);
 }
 
+// The polled fields of the control block into the host's mapped mirror.
+__global__ void k_mirror(const DevCtl *ctl, HostMirror *m) {
+    if (threadIdx.x == 0) {
+        m->err = ctl->err;
+        m->any_active = ctl->any_active;
+        __threadfence_system();
+    }
+}
+
 int grid_for(int64_t n) {
     int64_t g = (n + kWG - 1) / kWG;
     if (g < 1)
@@ -1166,6 +1175,11 @@ hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_li
     hipLaunchKernelGGL(k_correct, dim3(grid_for(slot_space)), dim3(kWG), 0, s, st, pr, i_list,
                        slots_at_offsets, off, cid, n_cur, t_cur, slot_space, acc_new, jerk_new,
                        in_stride, ctl);
+    return hipGetLastError();
+}
+
+hipError_t launch_mirror(const DevCtl *ctl, HostMirror *mirror_dev, hipStream_t s) {
+    hipLaunchKernelGGL(k_mirror, dim3(1), dim3(64), 0, s, ctl, mirror_dev);
     return hipGetLastError();
 }
 

@@ -72,6 +72,11 @@ struct nbody_ctx {
 
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
+    // mapped pinned memory the last kernel of each captured batch writes, so
+    // the stepping loop can poll it while the next batch is already queued
+    HostMirror *mirror_h = nullptr;
+    HostMirror *mirror_d = nullptr;
+    hipEvent_t batch_ev[2] = {nullptr, nullptr};
 };
 
 namespace {
@@ -446,6 +451,8 @@ int build_graph(nbody_ctx *c) {
     if (e == hipSuccess) {
         for (int s = 0; s < kGraphBatch && e == hipSuccess; s++)
             e = enqueue_block_step(c);
+        if (e == hipSuccess)
+            e = launch_mirror(c->ctl, c->mirror_d, c->stream);
         hipGraph_t g = nullptr;
         hipError_t e2 = hipStreamEndCapture(cap, &g);
         if (e == hipSuccess)
@@ -631,6 +638,19 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
         (e = hipMemcpy(c->chunk_c_d, chunk_c.data(), c->n_chunks * sizeof(int32_t), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(c->chunk_b_d, chunk_b.data(), c->n_chunks * sizeof(int64_t), hipMemcpyHostToDevice)) != hipSuccess)
         return fail(e);
+    {
+        void *hm = nullptr;
+        if ((e = hipHostMalloc(&hm, sizeof(HostMirror), hipHostMallocMapped)) != hipSuccess)
+            return fail(e);
+        c->mirror_h = static_cast<HostMirror *>(hm);
+        void *dm = nullptr;
+        if ((e = hipHostGetDevicePointer(&dm, hm, 0)) != hipSuccess)
+            return fail(e);
+        c->mirror_d = static_cast<HostMirror *>(dm);
+        for (int q = 0; q < 2; q++)
+            if ((e = hipEventCreateWithFlags(&c->batch_ev[q], hipEventDisableTiming)) != hipSuccess)
+                return fail(e);
+    }
     DevCtl h{};
     h.t_end_tick = LLONG_MAX;
     if ((e = hipMemcpy(c->ctl, &h, sizeof(h), hipMemcpyHostToDevice)) != hipSuccess)
@@ -662,6 +682,11 @@ int nbody_destroy(nbody_ctx *c) {
     drop_graph(c);
     for (void *p : c->allocs)
         (void)hipFree(p);
+    for (int q = 0; q < 2; q++)
+        if (c->batch_ev[q])
+            (void)hipEventDestroy(c->batch_ev[q]);
+    if (c->mirror_h)
+        (void)hipHostFree(c->mirror_h);
     delete c;
     return NBODY_OK;
 }
@@ -830,16 +855,28 @@ int nbody_run_until(nbody_ctx *c, double t_end, int64_t *n_steps_out) {
     if (h.err)
         return consume_error(c, h);
     const unsigned long long steps0 = h.steps;
+    // Two batches in flight: while batch k runs, batch k+1 is already queued,
+    // so the GPU does not wait for the host to look at batch k's outcome.
+    // Batches after the last active step plan nothing and exit at once.
+    c->mirror_h->err = 0;
+    c->mirror_h->any_active = 1;
+    int64_t launched = 0, waited = 0;
     for (;;) {
-        NB_TRY(hipGraphLaunch(c->graph_exec, c->stream));
-        rc = read_ctl(c, &h);
-        if (rc != NBODY_OK)
-            return rc;
-        if (h.err)
-            break;
-        if (!h.any_active)
+        while (launched - waited < 2) {
+            NB_TRY(hipGraphLaunch(c->graph_exec, c->stream));
+            NB_TRY(hipEventRecord(c->batch_ev[launched & 1], c->stream));
+            launched++;
+        }
+        NB_TRY(hipEventSynchronize(c->batch_ev[waited & 1]));
+        waited++;
+        // the mirror holds the end of batch `waited` or of a later one
+        const volatile HostMirror *m = c->mirror_h;
+        if (m->err || !m->any_active)
             break;
     }
+    rc = read_ctl(c, &h);  // waits for the batch still in flight
+    if (rc != NBODY_OK)
+        return rc;
     c->predicted = false;
     if (n_steps_out)
         *n_steps_out = (int64_t)(h.steps - steps0);

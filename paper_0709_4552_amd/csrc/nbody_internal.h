@@ -44,6 +44,13 @@ struct DevCtl {
     int32_t pad2;
 };
 
+// Host-visible copy of the fields the stepping loop polls (written by the last
+// kernel of each captured batch of block steps into mapped pinned memory).
+struct HostMirror {
+    int32_t err;
+    int32_t any_active;
+};
+
 constexpr int kMaxSlices = 1024;   // j-slices per cluster the planner may choose
 // Workgroups of one launch do not run at equal speed, so when each takes a
 // single long item the slowest sets the launch time.  The planner therefore
@@ -329,6 +336,7 @@ hipError_t launch_init_finish(const State &st, const Params &pr, const double *a
                               hipStream_t s);
 hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, double *vel,
                                  hipStream_t s);
+hipError_t launch_mirror(const DevCtl *ctl, HostMirror *mirror_dev, hipStream_t s);
 
 // ---- force (kernels_force.hip) --------------------------------------------
 bool force_shape_supported(const Shape &sh);
