@@ -168,6 +168,22 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
         return;
     if (FUSE)
         fused = ((fa.fused_mask >> cls_now) & 1) != 0;
+    if (fa.flip_lists) {
+        // block step: the block has been gathered from the due levels' lists
+        // and the corrector has not started, so nothing else touches the lists
+        // now: each due level changes to its other buffer, emptied, which the
+        // corrector then fills with the particles stepped onto that level
+        for (int64_t q = (int64_t)blockIdx.x * kWG + tid; q < (int64_t)fa.C * kLevels;
+             q += (int64_t)gridDim.x * kWG) {
+            const int cq = (int)(q / kLevels), L = (int)(q % kLevels);
+            if (L >= fa.ll.lev_min && L <= fa.lev_max && fa.n_cur[cq] > 0 &&
+                (fa.t_cur[cq] & ((int64_t(1) << (fa.lev_max - L)) - 1)) == 0) {
+                const int b = 1 - fa.ll.buf[q];
+                fa.ll.buf[q] = b;
+                fa.ll.cnt[((int64_t)b * fa.C + cq) * kLevels + L] = 0;
+            }
+        }
+    }
     const int64_t total = uniform_i64(*fa.total_items);
     // first round static (item = workgroup index); only when there are more
     // items than workgroups do finished workgroups pop further items from the

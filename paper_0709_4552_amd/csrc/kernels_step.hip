@@ -128,15 +128,30 @@ __device__ inline int64_t level_next(int64_t t_now, int shift) {
     return ((t_now >> shift) + 1) << shift;  // arithmetic shift: floor, also for t_now = -1
 }
 
+// Level L (lev_min <= L <= lev_max) is due at block time T when its step
+// divides T.
+__device__ inline bool level_due(const Params &pr, int L, int64_t T) {
+    return (T & (dt_ticks(pr.lev_max, L) - 1)) == 0;
+}
+
+__device__ inline int32_t *list_at(const LevelLists &ll, int b, int L, int64_t cb) {
+    return ll.idx + ((int64_t)b * ll.nlev + (L - ll.lev_min)) * ll.n_total + cb;
+}
+
+__device__ inline int32_t *list_cnt(const LevelLists &ll, int b, int c, int L) {
+    return ll.cnt + ((int64_t)b * ll.C + c) * kLevels + L;
+}
+
 // Priming scan before a run of block steps: level counts, earliest next time
 // and latest last time of each cluster.  A valid block-step state has every
 // last time before every next time and each last time a multiple of the
 // particle's step; anything else is flagged as not due.
 __global__ __launch_bounds__(kWG) void k_prime(State st, Params pr, const int64_t *off,
                                                const int32_t *chunk_c, const int64_t *chunk_b,
-                                               int32_t *lev_cnt, int64_t *t_min, int64_t *t_max,
-                                               DevCtl *ctl) {
+                                               int32_t *lev_cnt, LevelLists ll, int64_t *t_min,
+                                               int64_t *t_max, DevCtl *ctl) {
     __shared__ int32_t hist[kLevels];
+    __shared__ int32_t lbase[kLevels];
     __shared__ unsigned long long rmin[kWG / 64], rmax[kWG / 64];
     if (threadIdx.x < kLevels)
         hist[threadIdx.x] = 0;
@@ -148,8 +163,9 @@ __global__ __launch_bounds__(kWG) void k_prime(State st, Params pr, const int64_
     const int64_t i = b + threadIdx.x;
     unsigned long long nmin = ULLONG_MAX, tmax = 0;
     int32_t err = 0;
+    int lev = 0, rank = -1;
     if (i < e) {
-        const int lev = st.lev[i];
+        lev = st.lev[i];
         const int64_t tk = st.tick[i];
         if (lev < pr.lev_min || lev > pr.lev_max || tk < 0) {
             err = kErrNotDue;
@@ -157,7 +173,7 @@ __global__ __launch_bounds__(kWG) void k_prime(State st, Params pr, const int64_
             const int64_t dtk = dt_ticks(pr.lev_max, lev);
             if (tk & (dtk - 1))
                 err = kErrNotDue;
-            atomicAdd(&hist[lev], 1);
+            rank = atomicAdd(&hist[lev], 1);
             nmin = (unsigned long long)(tk + dtk);
             tmax = (unsigned long long)tk;
         }
@@ -182,8 +198,14 @@ __global__ __launch_bounds__(kWG) void k_prime(State st, Params pr, const int64_
         atomicMin((unsigned long long *)&t_min[c], nmin);
         atomicMax((unsigned long long *)&t_max[c], tmax);
     }
-    if (threadIdx.x < kLevels && hist[threadIdx.x] != 0)
+    // level counts, and each particle into the list of its level (buffer 0)
+    if (threadIdx.x < kLevels && hist[threadIdx.x] != 0) {
         atomicAdd(&lev_cnt[(int64_t)c * kLevels + threadIdx.x], hist[threadIdx.x]);
+        lbase[threadIdx.x] = atomicAdd(list_cnt(ll, 0, c, threadIdx.x), hist[threadIdx.x]);
+    }
+    __syncthreads();
+    if (rank >= 0)
+        list_at(ll, 0, lev, uniform_i64(off[c]))[lbase[lev] + rank] = (int32_t)i;
 }
 
 // t_now = (earliest next time) - 1: every level's next time computed from it is
@@ -197,51 +219,89 @@ __global__ void k_prime_finish(Params pr, const int64_t *t_min, const int64_t *t
     }
 }
 
-// One block step's scan (after the plan): predict every particle of a stepping
-// cluster to the block time and append the particles due then to the active
-// list.  One workgroup per chunk, one particle per thread.
+// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: row
+// shifts by 1, 2, 4 and 8, then the row broadcasts of lanes 15 and 31.  Lanes
+// whose shifted source lies outside their row add 0.  Every lane takes part.
+__device__ inline int64_t wave_inclusive_scan(int64_t v) {
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return v;
+}
+
+// The block of cluster c at block time T in slot order: the lists of its due
+// levels, levels ascending.  Wave 0 writes each level's buffer and the
+// exclusive prefix of the due counts to LDS (s_pre[64] = total) and returns
+// the total, which must equal the block size the level counts gave.
+__device__ inline int64_t due_prefix(const Params &pr, const LevelLists &ll, int c, int64_t T,
+                                     int32_t *s_buf, int32_t *s_pre) {
+    const int L = threadIdx.x & 63;
+    const bool in = L >= pr.lev_min && L <= pr.lev_max;
+    const int b = in ? ll.buf[(int64_t)c * kLevels + L] : 0;
+    const int32_t cnt = (in && level_due(pr, L, T)) ? *list_cnt(ll, b, c, L) : 0;
+    const int64_t incl = wave_inclusive_scan((int64_t)cnt);
+    s_buf[L] = b;
+    s_pre[L] = (int32_t)(incl - cnt);
+    if (L == 63)
+        s_pre[kLevels] = (int32_t)incl;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)incl, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)incl >> 32), 63);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Particle in slot k of the block (0 <= k < total): the level whose prefix
+// range holds k (the largest L with s_pre[L] <= k), then its place there.
+__device__ inline int32_t gather_slot(const LevelLists &ll, int64_t cb, int64_t k,
+                                      const int32_t *s_buf, const int32_t *s_pre) {
+    int lo = 0, hi = kLevels - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (s_pre[mid] <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return list_at(ll, s_buf[lo], lo, cb)[k - s_pre[lo]];
+}
+
+// One ensemble block step's scan (after the plan): predict every particle of
+// a stepping cluster to its block time and gather the cluster's block from its
+// level lists into the active list (slot of (c, k) = off[c] + k).  One
+// workgroup per chunk, one particle and one slot per thread.
 template <int MIXED>
-__global__ __launch_bounds__(kWG) void k_predict_compact(State st, Params pr, JBuf jb,
-                                                         const int64_t *off,
-                                                         const int32_t *chunk_c,
-                                                         const int64_t *chunk_b, PlanDev pl,
-                                                         int32_t *cursor, int32_t *i_list) {
+__global__ __launch_bounds__(kWG) void k_predict_gather(State st, Params pr, JBuf jb,
+                                                        const int64_t *off,
+                                                        const int32_t *chunk_c,
+                                                        const int64_t *chunk_b, PlanDev pl,
+                                                        LevelLists ll, int32_t *i_list,
+                                                        DevCtl *ctl) {
     static_assert(kChunk == kWG, "one particle per thread");
-    __shared__ int32_t wcount[kWG / 64];
-    __shared__ int32_t base_s;
+    __shared__ int32_t s_buf[kLevels], s_pre[kLevels + 1];
     const int64_t k = blockIdx.x;
     const int c = uniform_i32(chunk_c[k]);
-    if (uniform_i32(pl.n_cur[c]) == 0)
+    const int64_t n = uniform_i32(pl.n_cur[c]);
+    if (n == 0)
         return;
     const int64_t T = uniform_i64(pl.t_cur[c]);
     const int64_t cb = uniform_i64(off[c]);
     const int64_t b = uniform_i64(chunk_b[k]);
     const int64_t e = min(uniform_i64(off[c + 1]), b + kChunk);
+    if (threadIdx.x < 64) {
+        const int64_t tot = due_prefix(pr, ll, c, T, s_buf, s_pre);
+        if (b == cb && threadIdx.x == 0 && tot != n)
+            atomicOr(&ctl->err, kErrPlan);
+    }
+    __syncthreads();
     const int64_t i = b + threadIdx.x;
-    bool due = false;
     if (i < e) {
-        const int64_t tk = st.tick[i];
-        due = tk + dt_ticks(pr.lev_max, st.lev[i]) == T;
         predict_one<MIXED>(st, pr, jb, i, T);
+        // (a list total other than n has been flagged; gather no slot past it)
+        if (i - cb < n && i - cb < s_pre[kLevels])
+            i_list[i] = gather_slot(ll, cb, i - cb, s_buf, s_pre);
     }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const unsigned long long bal = __ballot(due);
-    const int before = __popcll(bal & ((1ull << lane) - 1ull));
-    if (lane == 0)
-        wcount[w] = __popcll(bal);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int q = 0; q < kWG / 64; q++) {
-            const int cnt = wcount[q];
-            wcount[q] = tot;
-            tot += cnt;
-        }
-        base_s = tot ? atomicAdd(&cursor[c], tot) : 0;
-    }
-    __syncthreads();
-    if (due)
-        i_list[cb + base_s + wcount[w] + before] = (int32_t)i;
 }
 
 // ---------------------------------------------------------------- planning
@@ -264,19 +324,6 @@ __device__ inline int32_t block_from_levels(const Params &pr, const PlanDev &pl,
                 n += cnt[L];
     *T_out = n > 0 ? T : tnow;
     return n;
-}
-
-// Inclusive prefix sum over the 64 lanes of a wave with DPP moves: row
-// shifts by 1, 2, 4 and 8, then the row broadcasts of lanes 15 and 31.  Lanes
-// whose shifted source lies outside their row add 0.  Every lane takes part.
-__device__ inline int64_t wave_inclusive_scan(int64_t v) {
-    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
-    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
-    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
-    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
-    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15
-    v += __builtin_amdgcn_update_dpp((int64_t)0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31
-    return v;
 }
 
 // Exclusive prefix sum over the kPlanThreads threads of the workgroup, and the
@@ -340,7 +387,6 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(Params pr, const int64_t 
             n = block_from_levels(pr, pl, c, t_end, &T);
             pl.t_cur[c] = T;
             pl.t_now[c] = T;
-            n_act[c] = 0;  // compaction cursor
         }
         pl.n_cur[c] = n;
         const double nc = (double)(off[c + 1] - off[c]);
@@ -610,76 +656,44 @@ __global__ __launch_bounds__(64) void k_plan_one(Params pr, const int64_t *off, 
 
 // One cluster, one block step's first kernel: every wave finds the next block
 // from the level counts (so no workgroup waits for another), workgroup 0 also
-// writes the plan, and every workgroup predicts its kPredictRounds * 256
-// particles to the block time (particle b + r*256 + thread in round r) and
-// appends the due ones to the active list, in (round, wave, lane) order after
-// one atomic on the cursor per workgroup.  The compaction cursor starts at
-// zero (reset by the previous step's corrector or by priming), and the
+// writes the plan, and every thread predicts one particle to the block time
+// and gathers one slot of the block from the due levels' lists.  The
 // cluster's time advances in the corrector, after every workgroup here has
 // read it.
-constexpr int kPredictRounds = 4;
-
 template <int MIXED>
-__global__ __launch_bounds__(kWG) void k_plan_predict_compact(State st, Params pr, JBuf jb,
-                                                              const int64_t *off, PlanDev pl,
-                                                              int32_t *cursor, int32_t *i_list,
-                                                              DevCtl *ctl, int64_t part_cap,
-                                                              ClassTable ct, int32_t fused_mask) {
-    constexpr int R = kPredictRounds, W = kWG / 64;
-    __shared__ int32_t wcount[R * W];
-    __shared__ int32_t base_s;
+__global__ __launch_bounds__(kWG) void k_plan_predict_gather(State st, Params pr, JBuf jb,
+                                                             const int64_t *off, PlanDev pl,
+                                                             LevelLists ll, int32_t *i_list,
+                                                             DevCtl *ctl, int64_t part_cap,
+                                                             ClassTable ct, int32_t fused_mask) {
+    __shared__ int32_t s_buf[kLevels], s_pre[kLevels + 1];
     int64_t T, n;
     next_block_wave(pr, pl, uniform_i64(ctl->t_end_tick), &T, &n);
     if (blockIdx.x == 0 && threadIdx.x < 64)
         plan_single_wave(off, pl, ctl, part_cap, ct, n, T, 1);
     if (n == 0)  // the same in every wave: they all read the same counts
         return;
+    if (threadIdx.x < 64) {
+        const int64_t tot = due_prefix(pr, ll, 0, T, s_buf, s_pre);
+        if (blockIdx.x == 0 && threadIdx.x == 0 && tot != n)
+            atomicOr(&ctl->err, kErrPlan);
+    }
+    __syncthreads();
     // blocks of a class whose force kernel predicts in the kernel need no
-    // prediction pass: only the compaction (the planner's class rule)
+    // prediction pass (the planner's class rule)
     int cls = kClasses - 1;
-    for (int k = 0; k < kClasses; k++)
-        if (n >= ct.min_n[k]) {
-            cls = k;
+    for (int q = 0; q < kClasses; q++)
+        if (n >= ct.min_n[q]) {
+            cls = q;
             break;
         }
     const bool predict = ((fused_mask >> cls) & 1) == 0;
-    const int64_t N = pr.n_total;
-    const int64_t b = (int64_t)blockIdx.x * (R * kWG) + threadIdx.x;
-    bool due[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const int64_t i = b + r * kWG;
-        due[r] = false;
-        if (i < N) {
-            due[r] = st.tick[i] + dt_ticks(pr.lev_max, st.lev[i]) == T;
-            if (predict)
-                predict_one<MIXED>(st, pr, jb, i, T);
-        }
-    }
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int before[R];
-#pragma unroll
-    for (int r = 0; r < R; r++) {
-        const unsigned long long bal = __ballot(due[r]);
-        before[r] = __popcll(bal & ((1ull << lane) - 1ull));
-        if (lane == 0)
-            wcount[r * W + w] = __popcll(bal);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int tot = 0;
-        for (int q = 0; q < R * W; q++) {
-            const int cnt = wcount[q];
-            wcount[q] = tot;
-            tot += cnt;
-        }
-        base_s = tot ? atomicAdd(&cursor[0], tot) : 0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < R; r++)
-        if (due[r])
-            i_list[base_s + wcount[r * W + w] + before[r]] = (int32_t)(b + r * kWG);
+    const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
+    if (i < pr.n_total && predict)
+        predict_one<MIXED>(st, pr, jb, i, T);
+    // (a list total other than n has been flagged; gather no slot past it)
+    if (i < n && i < s_pre[kLevels])
+        i_list[i] = gather_slot(ll, 0, i, s_buf, s_pre);
 }
 
 // ---------------------------------------------------------------- corrector
@@ -815,9 +829,37 @@ struct CorrArgs {
     const int64_t *t_cur;
     int64_t *t_now;
     int32_t *lev_cnt;
-    int32_t *cursor;  // compaction count of the step (checked against the plan)
+    LevelLists ll;
     DevCtl *ctl;
 };
+
+// Append each lane's corrected particle i (new level nl >= 0, cluster c) to
+// the current list of its new level (the force launch of the step has given
+// the due levels fresh, empty lists).  One atomic per (cluster, level) per
+// wave; every lane of the wave that is running must call it.
+__device__ inline void list_append(const CorrArgs &ca, const int64_t *off, int c, int nl,
+                                   int64_t i) {
+    const int lane = threadIdx.x & 63;
+    uint64_t pending = __ballot(nl >= 0);
+    while (pending) {
+        const int leader = __ffsll((unsigned long long)pending) - 1;
+        const int kc = __builtin_amdgcn_readlane(c, leader);
+        const int kl = __builtin_amdgcn_readlane(nl, leader);
+        const uint64_t m = __ballot(nl >= 0 && c == kc && nl == kl) & pending;
+        int base = 0, tb = 0;
+        if (lane == leader) {
+            tb = ca.ll.buf[(int64_t)kc * kLevels + kl];
+            base = atomicAdd(list_cnt(ca.ll, tb, kc, kl), (int)__popcll(m));
+        }
+        base = __builtin_amdgcn_readlane(base, leader);
+        tb = __builtin_amdgcn_readlane(tb, leader);
+        if ((m >> lane) & 1ull) {
+            const int rank = (int)__popcll(m & ((1ull << lane) - 1ull));
+            list_at(ca.ll, tb, kl, off[kc])[base + rank] = (int32_t)i;
+        }
+        pending &= ~m;
+    }
+}
 
 template <bool CORR>
 __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *cid,
@@ -825,17 +867,43 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                                                   CorrArgs ca) {
     __shared__ double red[7][kWG / 64];
     __shared__ int32_t dlev[kLevels];
+    // one cluster: the workgroup's list appends, staged in LDS and written at
+    // the end with one atomic per level (particle; level << 16 | rank)
+    constexpr int kStage = CORR ? 1024 : 1;
+    __shared__ int32_t s_si[kStage], s_sr[kStage];
+    __shared__ int32_t s_lcnt[kLevels], s_lbase[kLevels];
+    __shared__ int32_t s_ns;
     const int smax = uniform_i32(*s_max);
     if (!CORR && smax <= 1)
         return;
     if (CORR) {
-        if (threadIdx.x < kLevels)
+        if (threadIdx.x < kLevels) {
             dlev[threadIdx.x] = 0;
+            s_lcnt[threadIdx.x] = 0;
+        }
+        if (threadIdx.x == 0)
+            s_ns = 0;
         __syncthreads();
     }
     int32_t err = 0;
     unsigned long long clamps = 0;
-    auto emit = [&](int64_t s, int c, const double *v) {
+    // a corrected particle of a single cluster into the LDS stage (beyond its
+    // capacity straight into its list)
+    auto stage = [&](int nl, int64_t i) {
+        const int q = atomicAdd(&s_ns, 1);
+        if (q < kStage) {
+            const int r = atomicAdd(&s_lcnt[nl], 1);
+            s_si[q] = (int32_t)i;
+            s_sr[q] = (nl << 16) | r;
+        } else {
+            const int b = ca.ll.buf[nl];
+            const int pos = atomicAdd(list_cnt(ca.ll, b, 0, nl), 1);
+            list_at(ca.ll, b, nl, 0)[pos] = (int32_t)i;
+        }
+    };
+    // store a slot's sums, or (CORR) correct its particle; returns the new
+    // level (-1: nothing corrected) and the particle in *ip
+    auto emit = [&](int64_t s, int c, const double *v, int64_t *ip) -> int {
         if (!CORR) {
             fa.out_acc[s] = v[0];
             fa.out_acc[fa.out_stride + s] = v[1];
@@ -845,12 +913,12 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
             fa.out_jerk[2 * fa.out_stride + s] = v[5];
             if (fa.out_pot)
                 fa.out_pot[s] = v[6];
-            return;
+            return -1;
         }
         const int64_t i = fa.i_list[s];
         if (i < fa.off[c] || i >= fa.off[c + 1]) {
             err |= kErrRange;
-            return;
+            return -1;
         }
         const int old = ca.st.lev[i];
         const int nl = correct_particle(ca.st, ca.pr, i, ca.t_cur[c], v, v + 3, err, clamps);
@@ -863,6 +931,8 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                 atomicAdd(&ca.lev_cnt[(int64_t)c * kLevels + nl], 1);
             }
         }
+        *ip = i;
+        return nl;
     };
     // the force kernel's own output for a slot of a cluster that was not split
     auto direct = [&](int64_t s, double *v) {
@@ -892,10 +962,20 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
             if (k >= n)
                 continue;
             if (S <= 1) {
+                int nl = -1;
+                int64_t ip = 0;
                 if (CORR && t == 0) {
                     double v[7];
                     direct(s, v);
-                    emit(s, c, v);
+                    nl = emit(s, c, v, &ip);
+                }
+                if (CORR) {
+                    if (fa.C == 1) {
+                        if (nl >= 0)
+                            stage(nl, ip);
+                    } else if (w == 0) {
+                        list_append(ca, fa.off, c, nl, ip);
+                    }
                 }
                 continue;
             }
@@ -914,11 +994,21 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                     red[q][w] = v[q];
             }
             __syncthreads();
+            int nl = -1;
+            int64_t ip = 0;
             if (t == 0) {
 #pragma unroll
                 for (int q = 0; q < 7; q++)
                     v[q] = ((red[q][0] + red[q][1]) + red[q][2]) + red[q][3];
-                emit(s, c, v);
+                nl = emit(s, c, v, &ip);
+            }
+            if (CORR) {
+                if (fa.C == 1) {
+                    if (nl >= 0)
+                        stage(nl, ip);
+                } else if (w == 0) {
+                    list_append(ca, fa.off, c, nl, ip);
+                }
             }
             __syncthreads();
         }
@@ -956,10 +1046,20 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                 for (int q = 0; q < 7; q++)
                     v[q] = group_sum_rt(v[q], L);
             }
+            int nl = -1;
+            int64_t ip = 0;
             if (live && l == L - 1) {
                 if (S <= 1)
                     direct(s, v);
-                emit(s, c, v);
+                nl = emit(s, c, v, &ip);
+            }
+            if (CORR) {
+                if (fa.C == 1) {
+                    if (nl >= 0)
+                        stage(nl, ip);
+                } else {
+                    list_append(ca, fa.off, c, nl, ip);
+                }
             }
         }
     }
@@ -971,16 +1071,21 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
             atomicOr(&ca.ctl->err, err);
         if (clamps)
             atomicAdd(&ca.ctl->clamps, clamps);
-        if (fa.C == 1 && blockIdx.x == 0 && threadIdx.x == 0) {
-            // one cluster: check the compaction against the plan, then close the
-            // step (cursor back to zero, the cluster's time advances)
-            const int32_t n = fa.n_cur[0];
-            if (ca.cursor[0] != n)
-                atomicOr(&ca.ctl->err, kErrPlan);
-            ca.cursor[0] = 0;
-            if (n > 0)
-                ca.t_now[0] = ca.t_cur[0];
+        if (fa.C == 1 && s_ns > 0) {
+            // the staged appends: one atomic per level reserves the workgroup's
+            // places in each list
+            if (threadIdx.x < kLevels && s_lcnt[threadIdx.x] > 0)
+                s_lbase[threadIdx.x] = atomicAdd(
+                    list_cnt(ca.ll, ca.ll.buf[threadIdx.x], 0, threadIdx.x), s_lcnt[threadIdx.x]);
+            __syncthreads();
+            const int ns = min(s_ns, kStage);
+            for (int q = threadIdx.x; q < ns; q += kWG) {
+                const int L = s_sr[q] >> 16, r = s_sr[q] & 0xffff;
+                list_at(ca.ll, ca.ll.buf[L], L, 0)[s_lbase[L] + r] = s_si[q];
+            }
         }
+        if (fa.C == 1 && blockIdx.x == 0 && threadIdx.x == 0 && fa.n_cur[0] > 0)
+            ca.t_now[0] = ca.t_cur[0];  // one cluster: its time advances
     }
 }
 
@@ -1082,16 +1187,17 @@ hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, 
 
 hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
-                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, int32_t *cursor,
+                        const PlanDev &pl, const LevelLists &ll, int64_t *t_min, int64_t *t_max,
                         DevCtl *ctl, hipStream_t s) {
     hipError_t e;
     if ((e = launch_fill_i32(pl.lev_cnt, 0, (int64_t)pr.C * kLevels, s)) != hipSuccess ||
-        (e = launch_fill_i32(cursor, 0, pr.C, s)) != hipSuccess ||
+        (e = launch_fill_i32(ll.cnt, 0, 2 * (int64_t)pr.C * kLevels, s)) != hipSuccess ||
+        (e = launch_fill_i32(ll.buf, 0, (int64_t)pr.C * kLevels, s)) != hipSuccess ||
         (e = launch_fill_i64(t_min, LLONG_MAX, pr.C, s)) != hipSuccess ||
         (e = launch_fill_i64(t_max, 0, pr.C, s)) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_prime, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr, off, chunk_c,
-                       chunk_b, pl.lev_cnt, t_min, t_max, ctl);
+                       chunk_b, pl.lev_cnt, ll, t_min, t_max, ctl);
     if ((e = hipGetLastError()) != hipSuccess)
         return e;
     hipLaunchKernelGGL(k_prime_finish, dim3(grid_for(pr.C)), dim3(kWG), 0, s, pr, t_min, t_max,
@@ -1099,16 +1205,16 @@ hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
     return hipGetLastError();
 }
 
-hipError_t launch_predict_compact(const State &st, const Params &pr, const JBuf &jb,
-                                  const int64_t *off, const int32_t *chunk_c,
-                                  const int64_t *chunk_b, int64_t n_chunks, const PlanDev &pl,
-                                  int32_t *cursor, int32_t *i_list, hipStream_t s) {
+hipError_t launch_predict_gather(const State &st, const Params &pr, const JBuf &jb,
+                                 const int64_t *off, const int32_t *chunk_c,
+                                 const int64_t *chunk_b, int64_t n_chunks, const PlanDev &pl,
+                                 const LevelLists &ll, int32_t *i_list, DevCtl *ctl, hipStream_t s) {
     if (pr.precision == NBODY_PREC_MIXED)
-        hipLaunchKernelGGL(k_predict_compact<1>, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr,
-                           jb, off, chunk_c, chunk_b, pl, cursor, i_list);
+        hipLaunchKernelGGL(k_predict_gather<1>, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr,
+                           jb, off, chunk_c, chunk_b, pl, ll, i_list, ctl);
     else
-        hipLaunchKernelGGL(k_predict_compact<0>, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr,
-                           jb, off, chunk_c, chunk_b, pl, cursor, i_list);
+        hipLaunchKernelGGL(k_predict_gather<0>, dim3((unsigned)n_chunks), dim3(kWG), 0, s, st, pr,
+                           jb, off, chunk_c, chunk_b, pl, ll, i_list, ctl);
     return hipGetLastError();
 }
 
@@ -1128,20 +1234,19 @@ hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, 
     return hipGetLastError();
 }
 
-hipError_t launch_plan_predict_compact(const State &st, const Params &pr, const JBuf &jb,
-                                       const int64_t *off, const PlanDev &pl, int32_t *cursor,
-                                       int32_t *i_list, DevCtl *ctl, int64_t part_cap,
-                                       const ClassTable &ct, int32_t fused_mask, hipStream_t s) {
+hipError_t launch_plan_predict_gather(const State &st, const Params &pr, const JBuf &jb,
+                                      const int64_t *off, const PlanDev &pl, const LevelLists &ll,
+                                      int32_t *i_list, DevCtl *ctl, int64_t part_cap,
+                                      const ClassTable &ct, int32_t fused_mask, hipStream_t s) {
     if (pr.C != 1)
         return hipErrorInvalidValue;
-    const int64_t per_wg = (int64_t)kPredictRounds * kWG;
-    const unsigned g = (unsigned)((pr.n_total + per_wg - 1) / per_wg);
+    const unsigned g = (unsigned)((pr.n_total + kWG - 1) / kWG);
     if (pr.precision == NBODY_PREC_MIXED)
-        hipLaunchKernelGGL(k_plan_predict_compact<1>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off,
-                           pl, cursor, i_list, ctl, part_cap, ct, fused_mask);
+        hipLaunchKernelGGL(k_plan_predict_gather<1>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off, pl,
+                           ll, i_list, ctl, part_cap, ct, fused_mask);
     else
-        hipLaunchKernelGGL(k_plan_predict_compact<0>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off,
-                           pl, cursor, i_list, ctl, part_cap, ct, fused_mask);
+        hipLaunchKernelGGL(k_plan_predict_gather<0>, dim3(g), dim3(kWG), 0, s, st, pr, jb, off, pl,
+                           ll, i_list, ctl, part_cap, ct, fused_mask);
     return hipGetLastError();
 }
 
@@ -1154,14 +1259,14 @@ hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_s
 }
 
 hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Params &pr,
-                                 const int32_t *cid, const PlanDev &pl, int32_t *cursor,
+                                 const int32_t *cid, const PlanDev &pl, const LevelLists &ll,
                                  const int32_t *s_max, DevCtl *ctl, hipStream_t s) {
     // the grid is fixed when a step is captured: one thread per particle for
     // unsplit and narrow splits, grid-stride waves / workgroups for wider ones
     const int64_t n = pr.n_total;
     const int64_t g = std::min<int64_t>(4096, std::max<int64_t>((n + kWG - 1) / kWG,
                                                                 std::min<int64_t>(n, 1024)));
-    const CorrArgs ca{st, pr, pl.t_cur, pl.t_now, pl.lev_cnt, cursor, ctl};
+    const CorrArgs ca{st, pr, pl.t_cur, pl.t_now, pl.lev_cnt, ll, ctl};
     hipLaunchKernelGGL(k_reduce_t<true>, dim3((unsigned)g), dim3(kWG), 0, s, fa, cid, n, s_max,
                        ca);
     return hipGetLastError();

@@ -42,10 +42,11 @@ struct nbody_ctx {
     JBuf jb;
     int32_t *i_list_d = nullptr;
     int32_t *iota_d = nullptr;
-    int32_t *n_act_d = nullptr;   // host-set blocks; the block step's compaction cursor
+    int32_t *n_act_d = nullptr;   // host-set block sizes (explicit and start-up evaluations)
     int64_t *t_next_d = nullptr;  // host-set block times; earliest next time when priming
     int64_t *t_max_d = nullptr;   // latest last time when priming
     PlanDev pl{};
+    LevelLists ll{};  // particles by block-step level (the block of a step without a scan)
     double *acc_new = nullptr, *jerk_new = nullptr, *pot_new = nullptr;
     double *part = nullptr;
     int64_t part_cap = 0;
@@ -284,7 +285,7 @@ int consume_error(nbody_ctx *c, const DevCtl &h) {
 // (which the caller owns and the explicit entry points may have changed).
 hipError_t enqueue_prime(nbody_ctx *c) {
     return launch_prime(c->st, c->pr, c->off_d, c->chunk_c_d, c->chunk_b_d, c->n_chunks, c->pl,
-                        c->t_next_d, c->t_max_d, c->n_act_d, c->ctl, c->stream);
+                        c->ll, c->t_next_d, c->t_max_d, c->ctl, c->stream);
 }
 
 // One block step of every active cluster (section 4.1): plan the next block
@@ -304,23 +305,26 @@ hipError_t enqueue_block_step(nbody_ctx *c) {
                 fused |= 1 << k;
     hipError_t e;
     if (c->pr.C == 1) {
-        e = launch_plan_predict_compact(c->st, c->pr, c->jb, c->off_d, c->pl, c->n_act_d,
-                                        c->i_list_d, c->ctl, c->part_cap, ct, fused, c->stream);
+        e = launch_plan_predict_gather(c->st, c->pr, c->jb, c->off_d, c->pl, c->ll, c->i_list_d,
+                                       c->ctl, c->part_cap, ct, fused, c->stream);
     } else {
         e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl, c->part_cap, ct,
                         kPlanFromLevels, 0, 1, c->stream);
         if (e == hipSuccess)
-            e = launch_predict_compact(c->st, c->pr, c->jb, c->off_d, c->chunk_c_d, c->chunk_b_d,
-                                       c->n_chunks, c->pl, c->n_act_d, c->i_list_d, c->stream);
+            e = launch_predict_gather(c->st, c->pr, c->jb, c->off_d, c->chunk_c_d, c->chunk_b_d,
+                                      c->n_chunks, c->pl, c->ll, c->i_list_d, c->ctl, c->stream);
     }
     if (e != hipSuccess)
         return e;
     ForceArgs fa = force_args(c, c->i_list_d, 1, c->acc_new, c->jerk_new, nullptr, c->pr.n_total);
     fa.fused_mask = fused;
+    fa.ll = c->ll;
+    fa.flip_lists = 1;
+    fa.lev_max = c->pr.lev_max;
     e = launch_classes(c, fa, mixed, 0, excl, -1);
     if (e != hipSuccess)
         return e;
-    return launch_reduce_correct(fa, c->st, c->pr, c->cid_d, c->pl, c->n_act_d, &c->ctl->s_max,
+    return launch_reduce_correct(fa, c->st, c->pr, c->cid_d, c->pl, c->ll, &c->ctl->s_max,
                                  c->ctl, c->stream);
 }
 
@@ -623,6 +627,16 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
         (e = dalloc(c, &c->pot_new, N)) != hipSuccess ||
         (e = dalloc(c, &c->part, 7 * c->part_cap)) != hipSuccess ||
         (e = dalloc(c, &c->ctl, 1)) != hipSuccess || (e = dalloc(c, &c->nscale_d, C)) != hipSuccess)
+        return fail(e);
+    // level lists: two buffers of one list per level and cluster, each list
+    // able to hold its whole cluster
+    c->ll.nlev = pr.lev_max - pr.lev_min + 1;
+    c->ll.lev_min = pr.lev_min;
+    c->ll.C = (int32_t)C;
+    c->ll.n_total = N;
+    if ((e = dalloc(c, &c->ll.idx, 2 * (size_t)c->ll.nlev * N)) != hipSuccess ||
+        (e = dalloc(c, &c->ll.cnt, 2 * C * kLevels)) != hipSuccess ||
+        (e = dalloc(c, &c->ll.buf, C * kLevels)) != hipSuccess)
         return fail(e);
     if (mixed) {
         if ((e = dalloc(c, &c->jb.P, N)) != hipSuccess || (e = dalloc(c, &c->jb.Q, N)) != hipSuccess ||

@@ -97,6 +97,25 @@ struct State {
     int8_t *lev;
 };
 
+// The particles of each cluster by block-step level, so that a block step
+// finds its block without a scan (section 4.1, step 2: every particle on a
+// level whose step divides the block time is due, and nothing else).  List
+// (c, L) in buffer b holds cnt[b][c][L] particle indices of cluster c on
+// level L, at idx + (b*nlev + L - lev_min)*n_total + off[c].  A block step
+// gathers the lists of its due levels from buffer buf[c][L]; its force launch
+// then switches each due level to the other buffer, emptied (nothing reads or
+// writes the lists while it runs), and its corrector appends each corrected
+// particle to the current list of its new level.
+struct LevelLists {
+    int32_t *idx;      // [2][nlev][n_total]
+    int32_t *cnt;      // [2][C][kLevels]
+    int32_t *buf;      // [C][kLevels] current buffer of each list
+    int32_t nlev;      // lev_max - lev_min + 1
+    int32_t lev_min;
+    int32_t C;
+    int64_t n_total;
+};
+
 // Work plan of one force evaluation, built on the device by k_plan.
 struct PlanDev {
     int64_t *item_begin;   // [C+1] first work item of each cluster
@@ -170,6 +189,11 @@ struct ForceArgs {
     const double *hjx, *hjy, *hjz;  // |jerk_i| hint: the particle's stored jerk
     const double *m64;              // FP64 masses
     const float4 *nscale;           // [C] (largest mass, smallest mass, largest speed, 0)
+    // block steps: the level lists whose due levels this launch switches to
+    // fresh buffers (flip_lists = 0: explicit evaluations, no lists)
+    LevelLists ll;
+    int32_t flip_lists;
+    int32_t lev_max;
     float near_frac;                // 0 disables the near field
     float near_frac_jerk;           // 0 disables its jerk criterion
     uint32_t cls_lj;                // lane-group launches: log2(j lanes) of class k
@@ -306,25 +330,25 @@ hipError_t launch_predict(const State &st, const Params &pr, const JBuf &jb, con
                           int use_host_t, hipStream_t s);
 hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
-                        const PlanDev &pl, int64_t *t_min, int64_t *t_max, int32_t *cursor,
+                        const PlanDev &pl, const LevelLists &ll, int64_t *t_min, int64_t *t_max,
                         DevCtl *ctl, hipStream_t s);
-hipError_t launch_predict_compact(const State &st, const Params &pr, const JBuf &jb,
-                                  const int64_t *off, const int32_t *chunk_c,
-                                  const int64_t *chunk_b, int64_t n_chunks, const PlanDev &pl,
-                                  int32_t *cursor, int32_t *i_list, hipStream_t s);
+hipError_t launch_predict_gather(const State &st, const Params &pr, const JBuf &jb,
+                                 const int64_t *off, const int32_t *chunk_c,
+                                 const int64_t *chunk_b, int64_t n_chunks, const PlanDev &pl,
+                                 const LevelLists &ll, int32_t *i_list, DevCtl *ctl, hipStream_t s);
 hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, int32_t *n_act,
                        int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
                        int32_t host_n, int64_t host_t, int32_t count_stats, hipStream_t s);
 // fused_mask: classes whose force kernel predicts in the kernel; their blocks
 // skip the prediction pass (compaction only)
-hipError_t launch_plan_predict_compact(const State &st, const Params &pr, const JBuf &jb,
-                                       const int64_t *off, const PlanDev &pl, int32_t *cursor,
-                                       int32_t *i_list, DevCtl *ctl, int64_t part_cap,
-                                       const ClassTable &ct, int32_t fused_mask, hipStream_t s);
+hipError_t launch_plan_predict_gather(const State &st, const Params &pr, const JBuf &jb,
+                                      const int64_t *off, const PlanDev &pl, const LevelLists &ll,
+                                      int32_t *i_list, DevCtl *ctl, int64_t part_cap,
+                                      const ClassTable &ct, int32_t fused_mask, hipStream_t s);
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
                          const int32_t *s_max, hipStream_t s);
 hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Params &pr,
-                                 const int32_t *cid, const PlanDev &pl, int32_t *cursor,
+                                 const int32_t *cid, const PlanDev &pl, const LevelLists &ll,
                                  const int32_t *s_max, DevCtl *ctl, hipStream_t s);
 hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_list,
                           int32_t slots_at_offsets, const int64_t *off, const int32_t *cid,
