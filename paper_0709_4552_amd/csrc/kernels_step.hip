@@ -591,14 +591,29 @@ __device__ inline void plan_single_wave(const int64_t *off, const PlanDev &pl, D
     const int64_t tiles = (Nc + j_tile - 1) / j_tile;
     const int64_t nib = (n + ib_size - 1) / ib_size;
     const int64_t grid = plan_grid(grid_res, nib, tiles);
+    // every candidate S in 32-bit integers (tiles < 2^23 for any cluster the
+    // ABI allows, S <= kMaxSlices) and waves = ceil(nib*Seff/grid) in FP64
+    // (exact: the product is below 2^53, and a quotient that is not an
+    // integer lies at least 1/grid from one): software 64-bit divisions made
+    // this loop the longest part of a small block step's first kernel
+    const uint32_t tiles32 = (uint32_t)tiles;
+    const double nibd = (double)nib, inv_grid = 1.0 / (double)grid;
     int64_t key = INT64_MAX;
-    for (int64_t S = lane + 1; S <= kMaxSlices && S <= tiles; S += 64) {
-        if (n <= 0 || (S > 1 && S * n > part_cap))
+    for (uint32_t S = lane + 1; S <= (uint32_t)kMaxSlices && S <= tiles32; S += 64) {
+        if (n <= 0 || (S > 1 && (int64_t)S * n > part_cap))
             continue;
-        const int64_t tps = (tiles + S - 1) / S;
-        const int64_t Seff = (tiles + tps - 1) / tps;
-        const int64_t waves = (nib * Seff + grid - 1) / grid;
-        const int64_t k2 = ((waves * (tps + 1)) << 11) | (S - 1);
+        const uint32_t tps = (tiles32 + S - 1) / S;
+        const uint32_t Seff = (tiles32 + tps - 1) / tps;
+        const double q = nibd * (double)Seff;
+        double wv = ceil(q * inv_grid);
+        // the reciprocal product may round across an integer: step to the
+        // exact ceiling
+        if ((wv - 1.0) * (double)grid >= q)
+            wv -= 1.0;
+        else if (wv * (double)grid < q)
+            wv += 1.0;
+        const int64_t waves = (int64_t)wv;
+        const int64_t k2 = ((waves * (int64_t)(tps + 1)) << 11) | (int64_t)(S - 1);
         key = k2 < key ? k2 : key;
     }
     key = wave_min_i64(key);
@@ -980,14 +995,16 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                 continue;
             }
             const int64_t base = uniform_i64(fa.part_begin[c]) + k;
-            double v[7];
+            // all seven components' loads of a slice together, then the sums
+            double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int js = t; js < S; js += kWG) {
 #pragma unroll
-            for (int q = 0; q < 7; q++) {
-                double sum = 0.0;
-                for (int js = t; js < S; js += kWG)
-                    sum += fa.part[q * fa.part_cap + base + (int64_t)js * n];
-                v[q] = group_sum<64>(sum);
+                for (int q = 0; q < 7; q++)
+                    v[q] += fa.part[q * fa.part_cap + base + (int64_t)js * n];
             }
+#pragma unroll
+            for (int q = 0; q < 7; q++)
+                v[q] = group_sum<64>(v[q]);
             if (lane == 63) {
 #pragma unroll
                 for (int q = 0; q < 7; q++)
@@ -1252,8 +1269,11 @@ hipError_t launch_plan_predict_gather(const State &st, const Params &pr, const J
 
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
                          const int32_t *s_max, hipStream_t s) {
-    // enough waves for one per slot up to 4096 workgroups; grid-stride beyond
-    hipLaunchKernelGGL(k_reduce_t<false>, dim3(grid_for(slot_space * 64)), dim3(kWG), 0, s, fa,
+    // enough waves for one per slot up to 4096 workgroups (grid-stride
+    // beyond), and a workgroup per slot up to 1024 slots, so wide splits of
+    // small blocks are summed a workgroup per slot
+    const int64_t g = std::max<int64_t>(grid_for(slot_space * 64), std::min<int64_t>(slot_space, 1024));
+    hipLaunchKernelGGL(k_reduce_t<false>, dim3((unsigned)g), dim3(kWG), 0, s, fa,
                        cid, slot_space, s_max, CorrArgs{});
     return hipGetLastError();
 }
