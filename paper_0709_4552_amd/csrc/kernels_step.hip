@@ -837,6 +837,7 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
 // scheme current: level changes are gathered per workgroup in LDS (one
 // cluster) or added to the cluster's row directly (several).
 constexpr int64_t kReduceLanes = 1 << 17;
+constexpr int64_t kTileMin = 256;  // blocks of at least this many slots use slot tiles
 
 struct CorrArgs {
     State st;
@@ -881,6 +882,7 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                                                   int64_t slot_space, const int32_t *s_max,
                                                   CorrArgs ca) {
     __shared__ double red[7][kWG / 64];
+    __shared__ double tred[kWG / 64][7][64];  // slot tiles: each wave's quarter sums
     __shared__ int32_t dlev[kLevels];
     // one cluster: the workgroup's list appends, staged in LDS and written at
     // the end with one atomic per level (particle; level << 16 | rank)
@@ -967,7 +969,63 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
     else if (CORR)
         n_tot = uniform_i32(ca.ctl->n_last);
     const bool wg_mode = smax > 64 && (n_tot < 0 || n_tot <= (int64_t)gridDim.x);
-    if (wg_mode) {
+    // Large split blocks: a workgroup takes 64 consecutive slots (lane = slot,
+    // so a slice's loads are contiguous), wave w sums the slices of the w-th
+    // quarter in order, and the quarters are added in wave order through LDS.
+    const bool tile_mode = !wg_mode && smax > 4 && n_tot >= kTileMin;
+    if (tile_mode) {
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+        for (int64_t s0 = (int64_t)blockIdx.x * 64; s0 < bound; s0 += (int64_t)gridDim.x * 64) {
+            const int64_t s = s0 + lane;
+            int c = 0, S = 0;
+            int64_t k = 0, n = 0;
+            bool live = false;
+            if (s < bound) {
+                c = fa.C > 1 ? cid[s] : 0;
+                k = fa.slots_at_offsets ? s - fa.off[c] : s;
+                n = fa.n_cur[c];
+                S = fa.S[c];
+                live = k < n && (CORR || S > 1);
+            }
+            double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (live && S > 1) {
+                const int per = (S + 3) >> 2;
+                const int j0 = w * per, j1 = min(S, j0 + per);
+                const int64_t base = fa.part_begin[c] + k;
+                for (int js = j0; js < j1; js++) {
+#pragma unroll
+                    for (int q = 0; q < 7; q++)
+                        v[q] += fa.part[q * fa.part_cap + base + (int64_t)js * n];
+                }
+            }
+#pragma unroll
+            for (int q = 0; q < 7; q++)
+                tred[w][q][lane] = v[q];
+            __syncthreads();
+            int nl = -1;
+            int64_t ip = 0;
+            if (w == 0 && live) {
+                if (S > 1) {
+#pragma unroll
+                    for (int q = 0; q < 7; q++)
+                        v[q] = ((tred[0][q][lane] + tred[1][q][lane]) + tred[2][q][lane]) +
+                               tred[3][q][lane];
+                } else {
+                    direct(s, v);
+                }
+                nl = emit(s, c, v, &ip);
+            }
+            if (CORR) {
+                if (fa.C == 1) {
+                    if (nl >= 0)
+                        stage(nl, ip);
+                } else if (w == 0) {
+                    list_append(ca, fa.off, c, nl, ip);
+                }
+            }
+            __syncthreads();
+        }
+    } else if (wg_mode) {
         const int t = threadIdx.x, lane = t & 63, w = t >> 6;
         for (int64_t s = blockIdx.x; s < bound; s += gridDim.x) {
             const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
