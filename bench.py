@@ -433,20 +433,17 @@ def salpeter_bench(torch, n: int, t_end: float, cpu_check: bool):
 
 
 def perfmodel_bench(torch, n_list, t_end: float):
-    """The single-PC performance model of section 4.1 recast for one GPU.
-
-    The paper models one N-body time unit as a sum over block steps of
-    tau_pred*N + tau_force*n*N + tau_corr*n and fixes n at its average
-    0.20*N^0.81.  On the GPU each block step also has a fixed cost t0 (kernel
-    launches and their latency) and tau_force depends on n.  For every N this
-    measures the run to t_end (wall time, steps, updates, the sequence of block
-    sizes), tau_pred, tau_force(n) for n = 4^k, and tau_corr, then predicts the
-    run time two ways: the paper's form with the measured average block size,
-    and summed over the recorded block sizes.  t0 is fitted on the smallest N."""
+    """The single-PC performance model of section 4.1 recast for one GPU
+    (paper_0709_4552_amd.perfmodel): for every N this measures the run to t_end
+    (wall time, steps, updates, the sequence of block sizes), tau_pred,
+    tau_force(n) for n = 4^k and tau_corr, and predicts the run time summed over
+    the recorded block sizes and with the mean block size.  The per-step fixed
+    cost t0 is fitted on the smallest N alone; the other rows are held out."""
     import numpy as np
 
     from nbody_inputs import plummer
     from paper_0709_4552_amd import NBODY_PREC_MIXED, NBody
+    from paper_0709_4552_amd import perfmodel as pm
     eps = 1.0 / 256
     kw = dict(eta=0.01, eta_init=0.01, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -500,7 +497,7 @@ def perfmodel_bench(torch, n_list, t_end: float):
         # tau_pred: the predictor pass over all N
         restore()
         tau_pred = timed(g, lambda: g.predict(0.0), 20) / n_tot
-        # tau_force(n) at n = 4^k and at n = N
+        # tau_force(n) at n = 4^k and at n = N (one force call: plan, force, reduction)
         rng = np.random.Generator(np.random.PCG64(1006))
         grid_n = sorted(set([4 ** k for k in range(0, 20) if 4 ** k < n_tot] + [n_tot]))
         tau_f = {}
@@ -532,37 +529,36 @@ def perfmodel_bench(torch, n_list, t_end: float):
         gs.sync()
         gs.close()
         tau_corr = min(corr) / n_tot
-        ln = np.log(np.array(grid_n, dtype=np.float64))
-        lt = np.log(np.array([tau_f[n] for n in grid_n]))
-
-        def tau_force(n):
-            return float(np.exp(np.interp(np.log(np.maximum(n, 1)), ln, lt)))
-
         n_mean = updates / max(steps, 1)
         rows.append({"N": n_tot, "t_end": t_end, "T_app_s": t_app, "block_steps": int(steps),
                      "updates": int(updates), "interactions": inter, "n_mean": n_mean,
-                     "n_paper_0.20N^0.81": 0.20 * n_tot ** 0.81,
+                     "n_paper_0.20N^0.81": pm.block_size_paper(n_tot),
                      "tau_pred_us": tau_pred * 1e6, "tau_corr_us": tau_corr * 1e6,
                      "tau_force_us": {str(n): tau_f[n] * 1e6 for n in grid_n},
-                     "_force_sum_s": float(sum(tau_force(n) * n * n_tot for n in sizes)),
-                     "_force_mean_s": tau_force(n_mean) * inter,
-                     "_rest_s": steps * (tau_pred * n_tot) + updates * tau_corr})
+                     "_sizes": sizes, "_tau": pm.tau_force_table(tau_f),
+                     "_pred": tau_pred, "_corr": tau_corr})
         log(f"perfmodel N={n_tot}: T_app {t_app:.3f} s, {steps} steps, n_mean {n_mean:.1f} "
-            f"(0.20 N^0.81 = {0.20 * n_tot ** 0.81:.1f}), tau_pred {tau_pred * 1e9:.2f} ns, "
+            f"(0.20 N^0.81 = {pm.block_size_paper(n_tot):.1f}), tau_pred {tau_pred * 1e9:.2f} ns, "
             f"tau_corr {tau_corr * 1e9:.2f} ns")
-    # fixed cost per block step, from the smallest N (force work negligible there)
+    # fixed cost per block step, fitted on the smallest N alone
     r0 = rows[0]
-    t_fixed = (r0["T_app_s"] - r0["_force_sum_s"] - r0["_rest_s"]) / r0["block_steps"]
+    t_fixed = pm.fit_t0(r0["T_app_s"], r0["N"], r0["_sizes"], r0["_pred"], r0["_tau"], r0["_corr"])
     for r in rows:
+        sizes, tau = r.pop("_sizes"), r.pop("_tau")
+        tp, tc = r.pop("_pred"), r.pop("_corr")
         r["t0_us"] = t_fixed * 1e6
-        r["T_model_per_step_sizes_s"] = r["block_steps"] * t_fixed + r["_force_sum_s"] + r["_rest_s"]
-        r["T_model_mean_block_s"] = r["block_steps"] * t_fixed + r["_force_mean_s"] + r["_rest_s"]
+        r["T_model_per_step_sizes_s"] = pm.T_integrate(r["N"], sizes, tp, tau, tc, t_fixed)
+        r["T_model_mean_block_s"] = pm.T_integrate_mean(r["N"], r["block_steps"], r["n_mean"],
+                                                        tp, tau, tc, t_fixed)
         r["model_over_measured"] = r["T_model_per_step_sizes_s"] / r["T_app_s"]
-        for k in ("_force_sum_s", "_force_mean_s", "_rest_s"):
-            r[k.lstrip("_")] = r.pop(k)
+        r["held_out"] = r is not r0
         log(f"perfmodel N={r['N']}: T_app {r['T_app_s']:.3f} s, model (block sizes) "
-            f"{r['T_model_per_step_sizes_s']:.3f} s, model (mean block) {r['T_model_mean_block_s']:.3f} s")
+            f"{r['T_model_per_step_sizes_s']:.3f} s, model (mean block) "
+            f"{r['T_model_mean_block_s']:.3f} s{'' if r['held_out'] else ' (t0 fitted here)'}")
+    held = [r["model_over_measured"] for r in rows if r["held_out"]]
     return {"workload": f"plummer_eps1/256_mixed_to_t{t_end}", "t0_fitted_on_N": r0["N"],
+            "held_out_model_over_measured": {"min": min(held) if held else None,
+                                             "max": max(held) if held else None},
             "rows": rows}
 
 
@@ -577,28 +573,37 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=25.0,
                     help="CPU oracle budget; all N particles are checked when it suffices")
     ap.add_argument("--no-energy", action="store_true")
-    ap.add_argument("--blocksizes", type=int, default=0,
-                    help="also measure force-only rates per block size at this N (e.g. 1048576)")
-    ap.add_argument("--ensemble", type=int, default=0,
-                    help="also run the ensemble workload with this many clusters (e.g. 256)")
+    ap.add_argument("--blocksizes", type=int, default=1 << 20,
+                    help="force-only rates per block size at this N (0 = skip)")
+    ap.add_argument("--ensemble", type=int, default=256,
+                    help="the ensemble workload with this many clusters (0 = skip)")
     ap.add_argument("--ensemble-t", type=float, default=1.0 / 64)
-    ap.add_argument("--ensemble-full", type=float, default=0.0)
+    ap.add_argument("--ensemble-full", type=float, default=1.0)
     ap.add_argument("--no-per-cluster", action="store_true")
-    ap.add_argument("--perfmodel", type=str, default="",
-                    help="also fit and check the per-step performance model on these N "
-                         "(comma separated, e.g. 1024,4096,16384,65536,196608)")
+    ap.add_argument("--perfmodel", type=str, default="1024,4096,16384,65536,196608",
+                    help="fit and check the per-step performance model on these N "
+                         "(comma separated; empty = skip)")
     ap.add_argument("--perfmodel-t", type=float, default=1.0)
     ap.add_argument("--fused-mask", type=int, default=0b11100)
     ap.add_argument("--fused", type=int, default=0,
                     help="also time block steps with in-kernel prediction for the size "
                          "classes in this bit mask (e.g. 28 = classes 2-4), against the "
                          "prediction pass, this many times each")
-    ap.add_argument("--salpeter", type=int, default=0,
-                    help="also run a Salpeter-mass Plummer sphere of this N (e.g. 196608)")
+    ap.add_argument("--salpeter", type=int, default=196608,
+                    help="a Salpeter-mass Plummer sphere of this N (0 = skip)")
+    ap.add_argument("--quick", action="store_true",
+                    help="the headline workload only (no block sizes, ensemble, Salpeter, "
+                         "performance model)")
+    ap.add_argument("--only", type=str, default="",
+                    help="run just one of blocksizes, ensemble, salpeter, perfmodel and print "
+                         "its record (for profiler runs)")
     ap.add_argument("--sweep-only", type=int, default=0,
                     help="only time this many full sweeps, then one 512 MiB elementwise "
                          "copy of known size (for hardware-counter runs); prints one JSON line")
     args = ap.parse_args()
+    if args.quick:
+        args.blocksizes = args.ensemble = args.salpeter = 0
+        args.perfmodel = ""
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this library has no multi-GPU path "
               "(a sharded design over RCCL is described with the documentation)", file=sys.stderr)
@@ -609,6 +614,20 @@ def main():
 
     from nbody_inputs import plummer
     from paper_0709_4552_amd import NBODY_PREC_FP64, NBODY_PREC_MIXED
+
+    if args.only:
+        part = {"blocksizes": lambda: blocksize_sweep(torch, args.blocksizes or (1 << 20),
+                                                      not args.no_cpu_baseline),
+                "ensemble": lambda: ensemble_bench(torch, args.ensemble or 256, args.ensemble_t,
+                                                   args.ensemble_full, not args.no_per_cluster),
+                "salpeter": lambda: salpeter_bench(torch, args.salpeter or 196608, 1.0 / 16,
+                                                   not args.no_cpu_baseline),
+                "perfmodel": lambda: perfmodel_bench(
+                    torch, [int(q) for q in (args.perfmodel or "1024,196608").split(",")],
+                    args.perfmodel_t)}[args.only]()
+        print(json.dumps({"metric": METRIC, "mode": "only", "section": args.only,
+                          args.only: part}), flush=True)
+        return
 
     x, v, m = plummer(args.n, SEED)
     log(f"workload: Plummer N={args.n} seed={SEED} eps=1/1024 to t={T_END}")
