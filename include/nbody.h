@@ -60,11 +60,25 @@ extern "C" {
 #define NBODY_ERANGE (-7)       /* the device met a particle index out of range  */
 #define NBODY_EIO (-8)          /* checkpoint file not writable / readable / valid */
 #define NBODY_ESCRATCH (-9)     /* more particles than nbody_force_jerk_static holds */
+#define NBODY_EEXTENT (-10)     /* mixed: a particle 256 or more from its cluster's origin */
 
 /* arithmetic of the pairwise force sum */
 #define NBODY_PREC_FP64 0  /* every operation in FP64                             */
 #define NBODY_PREC_MIXED 1 /* FP64 coordinates and differences of positions,
                               FP32 pairwise terms, FP64 accumulation            */
+
+/*
+ * The mixed form stores each predicted position as a float on a 2^-16 grid
+ * plus a float remainder, both relative to an origin of the particle's
+ * cluster: the centre of the cluster's bounding box at nbody_init, rounded
+ * to a multiple of 64 (so a cluster around the coordinate origin keeps it),
+ * kept in checkpoints.  The grid parts are then exact, and so are their
+ * differences, while every coordinate stays less than 256 length units from
+ * the origin.  A prediction outside that range sets the device error word,
+ * reported as NBODY_EEXTENT by the next synchronising call: rescale the
+ * units, split the cluster, or use NBODY_PREC_FP64.  A cluster may lie
+ * anywhere, but must stay less than 512 units wide around its centre.
+ */
 
 typedef struct nbody_ctx nbody_ctx;
 
@@ -153,7 +167,9 @@ int nbody_destroy(nbody_ctx *ctx);
  * and jerk of every particle from all particles of its cluster (one full
  * n = N sweep), and give each particle its start-up block step: the largest
  * power of two not above eta_init |a|/|j|, clamped to the step range.
- * Resets the counters and the device error word.
+ * Resets the counters and the device error word, and (mixed form) sets each
+ * cluster's origin.  Errors: EEXTENT (mixed form, a cluster 512 or more
+ * units wide), ENONFINITE, EDEVICE.
  */
 int nbody_init(nbody_ctx *ctx);
 
@@ -195,8 +211,9 @@ int nbody_force_jerk(nbody_ctx *ctx, const int32_t *i_list_dev, int64_t n, doubl
 
 /*
  * Hermite corrector (section 4.1, step 5) for the n listed particles, which
- * must all be due at t (t_i + dt_i = t; otherwise the next synchronising
- * call returns ESTATE) and must be distinct.  acc_dev/jerk_dev hold the new
+ * must all be due at t (t_i + dt_i = t) and distinct; otherwise the next
+ * synchronising call returns ESTATE (a particle listed twice is corrected
+ * once, from the slot that claims it first).  acc_dev/jerk_dev hold the new
  * acceleration and jerk at t in the layout nbody_force_jerk writes.  Updates
  * pos, vel, acc, jerk, t_tick and level of those particles:
  *   a2 = [-6(a0-a1) - dt(4j0+2j1)]/dt^2,  a3 = [12(a0-a1) + 6dt(j0+j1)]/dt^3
@@ -334,6 +351,10 @@ int nbody_autotune(nbody_ctx *ctx, int64_t n_probe, nbody_tuning *best, double *
  *   before this time, e.g. from the previous evaluation; all six NULL: a first
  *   pass without the near field supplies them, doubling the work), and the
  *   masses are always tested pair by pair.  The FP64 form ignores the hints.
+ *   The mixed records take as origin the centre of the particles' bounding
+ *   box, rounded to a multiple of 64; particles 256 or more units from it
+ *   (a system 512 or more units wide) are outside the mixed form's error
+ *   bound, which this call cannot report: use the FP64 form for them.
  * i_list_dev, n, acc_dev, jerk_dev, pot_dev: as in nbody_force_jerk
  *   (pot_dev may be NULL); an index outside [0, n_j) leaves that slot's
  *   outputs unspecified (it is not reported: there is no context).

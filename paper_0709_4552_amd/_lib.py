@@ -22,6 +22,7 @@ NBODY_EUNSUPPORTED = -6
 NBODY_ERANGE = -7
 NBODY_EIO = -8
 NBODY_ESCRATCH = -9
+NBODY_EEXTENT = -10
 NBODY_STATIC_MAX_PARTICLES = 262144
 
 NBODY_PREC_FP64 = 0

@@ -107,7 +107,9 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
     auto fetch_m = [&](int64_t j, int64_t T, float4 &P, float4 &Q, float2 &R) {
         if (FUSE && fused) {
             float4 V;
-            predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, j, T, P, Q, R, V);
+            if (!predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, fa.origin[0], j, T, P, Q,
+                               R, V))
+                atomicOr(fa.err, kErrExtent);
         } else {
             P = fa.jb.P[j];
             Q = fa.jb.Q[j];
@@ -119,7 +121,8 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
         if (FUSE && fused) {
             float4 P, Q, V;
             float2 R;
-            predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, j, T, P, Q, R, V);
+            (void)predict_mixed(fa.st, fa.tick, fa.grid_q, fa.grid_inv, fa.origin[0], j, T, P, Q,
+                                R, V);
             return V;
         }
         return fa.jb.V[j];

@@ -47,19 +47,23 @@ __global__ void k_iota_i32(int32_t *p, int64_t n) {
 }
 
 // ---------------------------------------------------------------- predictor
-// Prediction of particle i to time T written to the j-particle buffer (the
-// arithmetic is shared with the force kernels' in-kernel prediction).
+// Prediction of particle i (of cluster c) to time T written to the
+// j-particle buffer (the arithmetic is shared with the force kernels'
+// in-kernel prediction).  False when a mixed record falls outside the exact
+// range around the cluster's origin.
 template <int MIXED>
-__device__ inline void predict_one(const State &st, const Params &pr, const JBuf &jb, int64_t i,
-                                   int64_t T) {
+__device__ inline bool predict_one(const State &st, const Params &pr, const JBuf &jb, int64_t i,
+                                   int64_t T, int c) {
     if (MIXED) {
         float4 P, Q, V;
         float2 R;
-        predict_mixed(st, pr.tick, pr.grid_q, pr.grid_inv, i, T, P, Q, R, V);
+        const bool ok = predict_mixed(st, pr.tick, pr.grid_q, pr.grid_inv, pr.origin[c], i, T, P,
+                                      Q, R, V);
         jb.P[i] = P;
         jb.Q[i] = Q;
         jb.R[i] = R;
         jb.V[i] = V;
+        return ok;
     } else {
         double2 A, B, C;
         double D;
@@ -68,6 +72,7 @@ __device__ inline void predict_one(const State &st, const Params &pr, const JBuf
         jb.B[i] = B;
         jb.C[i] = C;
         jb.D[i] = D;
+        return true;
     }
 }
 
@@ -76,30 +81,37 @@ __device__ inline void predict_one(const State &st, const Params &pr, const JBuf
 template <int MIXED>
 __global__ __launch_bounds__(kWG) void k_predict(State st, Params pr, JBuf jb, const int32_t *cid,
                                                   const int64_t *t_cur, const int32_t *n_cur,
-                                                  int64_t t_host, int use_host_t) {
+                                                  int64_t t_host, int use_host_t, DevCtl *ctl) {
+    bool ok = true;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < pr.n_total;
          i += (int64_t)gridDim.x * blockDim.x) {
+        const int c = pr.C > 1 ? cid[i] : 0;
         int64_t T = t_host;
         if (!use_host_t) {
-            const int c = pr.C > 1 ? cid[i] : 0;
             if (n_cur[c] == 0)
                 continue;
             T = t_cur[c];
         }
-        predict_one<MIXED>(st, pr, jb, i, T);
+        ok = predict_one<MIXED>(st, pr, jb, i, T, c) && ok;
     }
+    if (!ok)
+        atomicOr(&ctl->err, kErrExtent);
 }
 
-__global__ void k_read_predicted(Params pr, JBuf jb, double *pos, double *vel, int mixed) {
+// The predicted positions and velocities in the caller's frame (the mixed
+// records are relative to the cluster's origin).
+__global__ void k_read_predicted(Params pr, JBuf jb, const int32_t *cid, double *pos, double *vel,
+                                 int mixed) {
     const int64_t n = pr.n_total;
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         if (mixed) {
             const float4 p = jb.P[i], q = jb.Q[i];
             const float2 r = jb.R[i];
-            pos[i] = (double)p.x + (double)q.x;
-            pos[n + i] = (double)p.y + (double)q.y;
-            pos[2 * n + i] = (double)p.z + (double)q.z;
+            const double4 o = pr.origin[pr.C > 1 ? cid[i] : 0];
+            pos[i] = ((double)p.x + (double)q.x) + o.x;
+            pos[n + i] = ((double)p.y + (double)q.y) + o.y;
+            pos[2 * n + i] = ((double)p.z + (double)q.z) + o.z;
             vel[i] = q.w;
             vel[n + i] = r.x;
             vel[2 * n + i] = r.y;
@@ -297,7 +309,8 @@ __global__ __launch_bounds__(kWG) void k_predict_gather(State st, Params pr, JBu
     __syncthreads();
     const int64_t i = b + threadIdx.x;
     if (i < e) {
-        predict_one<MIXED>(st, pr, jb, i, T);
+        if (!predict_one<MIXED>(st, pr, jb, i, T, c))
+            atomicOr(&ctl->err, kErrExtent);
         // (a list total other than n has been flagged; gather no slot past it)
         if (i - cb < n && i - cb < s_pre[kLevels])
             i_list[i] = gather_slot(ll, cb, i - cb, s_buf, s_pre);
@@ -704,8 +717,8 @@ __global__ __launch_bounds__(kWG) void k_plan_predict_gather(State st, Params pr
         }
     const bool predict = ((fused_mask >> cls) & 1) == 0;
     const int64_t i = (int64_t)blockIdx.x * kWG + threadIdx.x;
-    if (i < pr.n_total && predict)
-        predict_one<MIXED>(st, pr, jb, i, T);
+    if (i < pr.n_total && predict && !predict_one<MIXED>(st, pr, jb, i, T, 0))
+        atomicOr(&ctl->err, kErrExtent);
     // (a list total other than n has been flagged; gather no slot past it)
     if (i < n && i < s_pre[kLevels])
         i_list[i] = gather_slot(ll, 0, i, s_buf, s_pre);
@@ -715,13 +728,14 @@ __global__ __launch_bounds__(kWG) void k_plan_predict_gather(State st, Params pr
 // Section 4.1, step 5: Hermite correction of particle i at time T from its new
 // acceleration and jerk, and its next step level (Aarseth criterion, then the
 // power-of-two quantisation).  Returns the new level, or -1 when the particle
-// was not due at T (then nothing is written).
+// was not due at T (then nothing is written).  claimed: the caller has already
+// moved the particle's tick to T itself (having checked that it was due).
 __device__ inline int correct_particle(const State &st, const Params &pr, int64_t i, int64_t T,
                                        const double a1[3], const double j1[3], int32_t &err,
-                                       unsigned long long &clamps) {
+                                       unsigned long long &clamps, bool claimed = false) {
     const int lev = st.lev[i];
     const int64_t dtk = dt_ticks(pr.lev_max, lev);
-    if (st.tick[i] + dtk != T) {
+    if (!claimed && st.tick[i] + dtk != T) {
         err |= kErrNotDue;
         return -1;
     }
@@ -803,13 +817,24 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
             err |= kErrRange;
             continue;
         }
+        // a caller's list may name a particle twice: the first slot to move
+        // its tick from the last step's time to T corrects it, any other
+        // finds it no longer due
+        const int64_t T = t_cur[c];
+        const int64_t due_from = T - dt_ticks(pr.lev_max, st.lev[i]);
+        if (atomicCAS(reinterpret_cast<unsigned long long *>(st.tick + i),
+                      (unsigned long long)due_from, (unsigned long long)T) !=
+            (unsigned long long)due_from) {
+            err |= kErrNotDue;
+            continue;
+        }
         double a1[3], j1[3];
 #pragma unroll
         for (int q = 0; q < 3; q++) {
             a1[q] = an[q * in_stride + s];
             j1[q] = jn[q * in_stride + s];
         }
-        (void)correct_particle(st, pr, i, t_cur[c], a1, j1, err, clamps);
+        (void)correct_particle(st, pr, i, T, a1, j1, err, clamps, true);
     }
     if (err)
         atomicOr(&ctl->err, err);
@@ -1242,21 +1267,21 @@ hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s) {
 
 hipError_t launch_predict(const State &st, const Params &pr, const JBuf &jb, const int32_t *cid,
                           const int64_t *t_cur, const int32_t *n_cur, int64_t t_host,
-                          int use_host_t, hipStream_t s) {
+                          int use_host_t, DevCtl *ctl, hipStream_t s) {
     const int g = grid_for(pr.n_total);
     if (pr.precision == NBODY_PREC_MIXED)
         hipLaunchKernelGGL(k_predict<1>, dim3(g), dim3(kWG), 0, s, st, pr, jb, cid, t_cur, n_cur,
-                           t_host, use_host_t);
+                           t_host, use_host_t, ctl);
     else
         hipLaunchKernelGGL(k_predict<0>, dim3(g), dim3(kWG), 0, s, st, pr, jb, cid, t_cur, n_cur,
-                           t_host, use_host_t);
+                           t_host, use_host_t, ctl);
     return hipGetLastError();
 }
 
-hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, double *vel,
-                                 hipStream_t s) {
-    hipLaunchKernelGGL(k_read_predicted, dim3(grid_for(pr.n_total)), dim3(kWG), 0, s, pr, jb, pos,
-                       vel, (int)(pr.precision == NBODY_PREC_MIXED));
+hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, const int32_t *cid,
+                                 double *pos, double *vel, hipStream_t s) {
+    hipLaunchKernelGGL(k_read_predicted, dim3(grid_for(pr.n_total)), dim3(kWG), 0, s, pr, jb, cid,
+                       pos, vel, (int)(pr.precision == NBODY_PREC_MIXED));
     return hipGetLastError();
 }
 

@@ -54,6 +54,8 @@ struct nbody_ctx {
     // [C] near-field scales of each cluster: largest mass, smallest mass,
     // largest speed (the mixed form's FP64 near-field test), from init / load
     float4 *nscale_d = nullptr;
+    // [C] origin of each cluster's mixed records (x, y, z, 0), from init / load
+    double4 *origin_d = nullptr;
 
     std::vector<void *> allocs;
 
@@ -195,6 +197,7 @@ ForceArgs force_args(nbody_ctx *c, const int32_t *i_list, int slots_at_offsets, 
     fa.tick = c->pr.tick;
     fa.grid_q = c->pr.grid_q;
     fa.grid_inv = c->pr.grid_inv;
+    fa.origin = c->origin_d;
     return fa;
 }
 
@@ -276,6 +279,8 @@ int consume_error(nbody_ctx *c, const DevCtl &h) {
         return NBODY_ERANGE;
     if (h.err & kErrNotDue)
         return NBODY_ESTATE;
+    if (h.err & kErrExtent)  // its records are off the grid: what follows is not trusted
+        return NBODY_EEXTENT;
     if (h.err & kErrNonFinite)
         return NBODY_ENONFINITE;
     return NBODY_EDEVICE;
@@ -369,14 +374,43 @@ hipError_t upload_cluster_scales(nbody_ctx *c, const double *mh, const double *v
     return hipMemcpy(c->nscale_d, sc.data(), sc.size() * sizeof(float4), hipMemcpyHostToDevice);
 }
 
+// Origins of the mixed records: the centre of each cluster's bounding box,
+// rounded to a multiple of 64 so that a cluster around the coordinate origin
+// keeps it (and its records their bits).  The FP64 form ignores them.
+hipError_t upload_origins(nbody_ctx *c, const double *xh, const double4 *saved = nullptr) {
+    const int64_t N = c->pr.n_total;
+    std::vector<double4> o(c->pr.C, make_double4(0.0, 0.0, 0.0, 0.0));
+    for (int k = 0; k < c->pr.C; k++) {
+        double ctr[3] = {0.0, 0.0, 0.0};
+        for (int q = 0; q < 3; q++) {
+            double lo = INFINITY, hi = -INFINITY;
+            for (int64_t i = c->off_h[k]; i < c->off_h[k + 1]; i++) {
+                const double x = xh[q * N + i];
+                if (std::isfinite(x)) {
+                    lo = std::min(lo, x);
+                    hi = std::max(hi, x);
+                }
+            }
+            if (lo <= hi)
+                ctr[q] = 64.0 * std::nearbyint((0.5 * lo + 0.5 * hi) * (1.0 / 64.0));
+        }
+        o[k] = make_double4(ctr[0], ctr[1], ctr[2], 0.0);
+    }
+    if (saved)
+        for (int k = 0; k < c->pr.C; k++)
+            o[k] = saved[k];
+    return hipMemcpy(c->origin_d, o.data(), o.size() * sizeof(double4), hipMemcpyHostToDevice);
+}
+
 // ---- checkpoint file ----
 // Little-endian binary: magic, version, the context's configuration (checked on
 // load), statistics, tuning table, the near-field scales of each cluster (4
-// floats), then the particle state as 13 FP64 arrays (x y z vx vy vz ax ay az
-// jx jy jz m), int64 ticks and int8 levels, and an FNV-1a 64-bit checksum of
-// everything after the magic.
+// floats), the origin of each cluster's mixed records (4 doubles; absent in
+// version 2, whose runs used the coordinate origin), then the particle state
+// as 13 FP64 arrays (x y z vx vy vz ax ay az jx jy jz m), int64 ticks and int8
+// levels, and an FNV-1a 64-bit checksum of everything after the magic.
 constexpr char kCkptMagic[8] = {'N', 'B', 'O', 'D', 'Y', 'C', 'K', 'P'};
-constexpr uint32_t kCkptVersion = 2;
+constexpr uint32_t kCkptVersion = 3;
 
 struct Fnv {
     uint64_t h = 1469598103934665603ull;
@@ -493,6 +527,8 @@ const char *nbody_strerror(int status) {
         case NBODY_ERANGE: return "particle index out of range";
         case NBODY_EIO: return "checkpoint file could not be written or read, or is damaged";
         case NBODY_ESCRATCH: return "more particles than the allocation-free evaluation holds";
+        case NBODY_EEXTENT:
+            return "mixed precision: a particle is 256 or more length units from its cluster's origin";
         default: return "unknown status";
     }
 }
@@ -626,8 +662,10 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
         (e = dalloc(c, &c->jerk_new, 3 * N)) != hipSuccess ||
         (e = dalloc(c, &c->pot_new, N)) != hipSuccess ||
         (e = dalloc(c, &c->part, 7 * c->part_cap)) != hipSuccess ||
-        (e = dalloc(c, &c->ctl, 1)) != hipSuccess || (e = dalloc(c, &c->nscale_d, C)) != hipSuccess)
+        (e = dalloc(c, &c->ctl, 1)) != hipSuccess || (e = dalloc(c, &c->nscale_d, C)) != hipSuccess ||
+        (e = dalloc(c, &c->origin_d, C)) != hipSuccess)
         return fail(e);
+    c->pr.origin = c->origin_d;
     // level lists: two buffers of one list per level and cluster, each list
     // able to hold its whole cluster
     c->ll.nlev = pr.lev_max - pr.lev_min + 1;
@@ -673,7 +711,9 @@ int nbody_create(const nbody_params *p, const nbody_state *s, void *stream, nbod
         // no near-field scales until init / load (the mixed force refuses to
         // run before either)
         const std::vector<float4> zero(C, make_float4(0.f, 0.f, 0.f, 0.f));
-        if ((e = hipMemcpy(c->nscale_d, zero.data(), C * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess)
+        const std::vector<double4> zero_o(C, make_double4(0.0, 0.0, 0.0, 0.0));
+        if ((e = hipMemcpy(c->nscale_d, zero.data(), C * sizeof(float4), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(c->origin_d, zero_o.data(), C * sizeof(double4), hipMemcpyHostToDevice)) != hipSuccess)
             return fail(e);
     }
     if ((e = launch_iota_i32(c->iota_d, N, c->stream)) != hipSuccess ||
@@ -723,20 +763,24 @@ int nbody_init(nbody_ctx *c) {
     NB_TRY(launch_fill_i64(c->st.tick, 0, N, c->stream));
     NB_TRY(launch_fill_i32(c->n_act_d, 0, c->pr.C, c->stream));
     NB_TRY(launch_fill_i64(c->t_next_d, LLONG_MAX, c->pr.C, c->stream));
-    NB_TRY(launch_predict(c->st, c->pr, c->jb, c->cid_d, nullptr, nullptr, 0, 1, c->stream));
+    {
+        std::vector<double> mh(N), xh(3 * N), vh(3 * N);
+        NB_TRY(hipStreamSynchronize(c->stream));
+        NB_TRY(hipMemcpy(mh.data(), c->st.m, N * sizeof(double), hipMemcpyDeviceToHost));
+        const double *xs[3] = {c->st.x, c->st.y, c->st.z};
+        const double *vs[3] = {c->st.vx, c->st.vy, c->st.vz};
+        for (int q = 0; q < 3; q++) {
+            NB_TRY(hipMemcpy(xh.data() + q * N, xs[q], N * sizeof(double), hipMemcpyDeviceToHost));
+            NB_TRY(hipMemcpy(vh.data() + q * N, vs[q], N * sizeof(double), hipMemcpyDeviceToHost));
+        }
+        NB_TRY(upload_cluster_scales(c, mh.data(), vh.data()));
+        NB_TRY(upload_origins(c, xh.data()));
+    }
+    NB_TRY(launch_predict(c->st, c->pr, c->jb, c->cid_d, nullptr, nullptr, 0, 1, c->ctl, c->stream));
     // full sweep of every cluster: active list = identity, n_c = N_c, t = 0
     std::vector<int32_t> nc(c->pr.C);
     for (int k = 0; k < c->pr.C; k++)
         nc[k] = (int32_t)(c->off_h[k + 1] - c->off_h[k]);
-    {
-        std::vector<double> mh(N), vh(3 * N);
-        NB_TRY(hipStreamSynchronize(c->stream));
-        NB_TRY(hipMemcpy(mh.data(), c->st.m, N * sizeof(double), hipMemcpyDeviceToHost));
-        const double *vs[3] = {c->st.vx, c->st.vy, c->st.vz};
-        for (int q = 0; q < 3; q++)
-            NB_TRY(hipMemcpy(vh.data() + q * N, vs[q], N * sizeof(double), hipMemcpyDeviceToHost));
-        NB_TRY(upload_cluster_scales(c, mh.data(), vh.data()));
-    }
     // mixed: a first sweep without near field gives |a| for the thresholds
     const int passes = c->pr.precision == NBODY_PREC_MIXED ? 2 : 1;
     for (int pass = 0; pass < passes; pass++) {
@@ -767,7 +811,8 @@ int nbody_predict(nbody_ctx *c, double t) {
     int64_t tick;
     if (!is_multiple_tick(t, c->pr.dt_min_log2, &tick))
         return NBODY_EINVAL;
-    NB_TRY(launch_predict(c->st, c->pr, c->jb, c->cid_d, nullptr, nullptr, tick, 1, c->stream));
+    NB_TRY(launch_predict(c->st, c->pr, c->jb, c->cid_d, nullptr, nullptr, tick, 1, c->ctl,
+                          c->stream));
     c->predicted = true;
     c->predicted_tick = tick;
     return NBODY_OK;
@@ -926,7 +971,7 @@ int nbody_read_predicted(nbody_ctx *c, double *pos, double *vel) {
         return NBODY_EINVAL;
     if (!c->predicted)
         return NBODY_ESTATE;
-    NB_TRY(launch_read_predicted(c->pr, c->jb, pos, vel, c->stream));
+    NB_TRY(launch_read_predicted(c->pr, c->jb, c->cid_d, pos, vel, c->stream));
     return NBODY_OK;
 }
 
@@ -1117,6 +1162,9 @@ int nbody_save(nbody_ctx *c, const char *path) {
     std::vector<float4> scales(c->pr.C);
     NB_TRY(hipMemcpy(scales.data(), c->nscale_d, scales.size() * sizeof(float4),
                      hipMemcpyDeviceToHost));
+    std::vector<double4> origins(c->pr.C);
+    NB_TRY(hipMemcpy(origins.data(), c->origin_d, origins.size() * sizeof(double4),
+                     hipMemcpyDeviceToHost));
 
     // write beside the target, then rename: an existing checkpoint is replaced
     // only by a complete one
@@ -1147,6 +1195,7 @@ int nbody_save(nbody_ctx *c, const char *path) {
         w.put(t, sizeof(t));
     }
     w.put(scales.data(), scales.size() * sizeof(float4));
+    w.put(origins.data(), origins.size() * sizeof(double4));
     w.put(buf.data(), buf.size() * sizeof(double));
     w.put(tick.data(), tick.size() * sizeof(int64_t));
     w.put(lev.data(), lev.size());
@@ -1181,7 +1230,7 @@ int nbody_load(nbody_ctx *c, const char *path) {
     CkptReader r{f};
     uint32_t ver = 0;
     r.get(&ver, sizeof(ver));
-    if (!r.ok || ver != kCkptVersion)
+    if (!r.ok || (ver != kCkptVersion && ver != 2))
         return done(NBODY_EIO);
     CkptConfig k{};
     r.get(&k.n_total, 8);
@@ -1224,15 +1273,19 @@ int nbody_load(nbody_ctx *c, const char *path) {
     std::vector<int64_t> tick;
     std::vector<int8_t> lev;
     std::vector<float4> scales;
+    std::vector<double4> origins;
     try {
         buf.resize(13 * (size_t)N);
         tick.resize(N);
         lev.resize(N);
         scales.resize(c->pr.C);
+        origins.assign(c->pr.C, make_double4(0.0, 0.0, 0.0, 0.0));
     } catch (const std::bad_alloc &) {
         return done(NBODY_ENOMEM);
     }
     r.get(scales.data(), scales.size() * sizeof(float4));
+    if (ver >= 3)
+        r.get(origins.data(), origins.size() * sizeof(double4));
     r.get(buf.data(), buf.size() * sizeof(double));
     r.get(tick.data(), tick.size() * sizeof(int64_t));
     r.get(lev.data(), lev.size());
@@ -1255,6 +1308,7 @@ int nbody_load(nbody_ctx *c, const char *path) {
     NB_TRY(hipMemcpy(st.tick, tick.data(), N * sizeof(int64_t), hipMemcpyHostToDevice));
     NB_TRY(hipMemcpy(st.lev, lev.data(), N * sizeof(int8_t), hipMemcpyHostToDevice));
     NB_TRY(upload_cluster_scales(c, buf.data() + 12 * N, buf.data() + 3 * N, scales.data()));
+    NB_TRY(upload_origins(c, buf.data(), origins.data()));
     DevCtl h;
     int rc = read_ctl(c, &h);
     if (rc != NBODY_OK)

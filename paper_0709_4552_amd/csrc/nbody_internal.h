@@ -24,6 +24,7 @@ enum : int32_t {
     kErrRange = 2,
     kErrNotDue = 4,
     kErrPlan = 8,
+    kErrExtent = 16,
 };
 
 // Device-resident counters and scalars, one instance per context.
@@ -140,6 +141,8 @@ struct Params {
     int32_t precision;
     double grid_q;                  // mixed: quantum of the hi part of positions
     double grid_inv;                // 1 / grid_q
+    const double4 *origin;          // mixed: [C] each cluster's origin (x, y, z, 0),
+                                    // subtracted before the hi/lo split
 };
 
 // Mixed precision near field: a pair whose acceleration term may exceed
@@ -153,6 +156,11 @@ struct Params {
 constexpr float kNearFrac = 0.1f;
 constexpr float kNearFracJerk = 2.0f;
 constexpr int kGridQLog2 = -16;  // hi parts on a 2^-16 grid: exact differences for |x| < 256
+// Positions are split relative to their cluster's origin.  Within
+// kMixedExtent of it every hi part is a float on the grid; a prediction
+// beyond it raises kErrExtent.
+constexpr double kMixedExtent = 256.0;
+static_assert(kMixedExtent == (double)(1 << (24 + kGridQLog2)), "24-bit hi parts");
 
 // Everything the force kernels need.
 struct ForceArgs {
@@ -205,6 +213,7 @@ struct ForceArgs {
     State st;
     const int64_t *t_cur;
     double tick, grid_q, grid_inv;
+    const double4 *origin;          // the cluster's origin (in-kernel prediction)
 };
 
 // Third-order Taylor prediction of particle i to tick T (section 4.1, step
@@ -247,12 +256,19 @@ __device__ inline void split_mixed(double xp, double yp, double zp, double vxp, 
                     (float)(vzp - (double)R.y), 0.f);
 }
 
-__device__ inline void predict_mixed(const State &st, double tick, double grid_q, double grid_inv,
-                                     int64_t i, int64_t T, float4 &P, float4 &Q, float2 &R,
-                                     float4 &V) {
+// The mixed record of particle i predicted to tick T, its position taken
+// relative to its cluster's origin o.  False when that relative position is
+// kMixedExtent or more from o on some axis (NaN passes: the corrector flags it).
+__device__ inline bool predict_mixed(const State &st, double tick, double grid_q, double grid_inv,
+                                     const double4 &o, int64_t i, int64_t T, float4 &P, float4 &Q,
+                                     float2 &R, float4 &V) {
     double xp, yp, zp, vxp, vyp, vzp;
     predict_terms(st, tick, i, T, xp, yp, zp, vxp, vyp, vzp);
+    xp -= o.x;
+    yp -= o.y;
+    zp -= o.z;
     split_mixed(xp, yp, zp, vxp, vyp, vzp, st.m[i], grid_q, grid_inv, P, Q, R, V);
+    return !(fabs(xp) >= kMixedExtent || fabs(yp) >= kMixedExtent || fabs(zp) >= kMixedExtent);
 }
 
 __device__ inline void predict_fp64(const State &st, double tick, int64_t i, int64_t T,
@@ -327,7 +343,7 @@ hipError_t launch_iota_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_set_i64(int64_t *p, int64_t v, hipStream_t s);
 hipError_t launch_predict(const State &st, const Params &pr, const JBuf &jb, const int32_t *cid,
                           const int64_t *t_cur, const int32_t *n_cur, int64_t t_host,
-                          int use_host_t, hipStream_t s);
+                          int use_host_t, DevCtl *ctl, hipStream_t s);
 hipError_t launch_prime(const State &st, const Params &pr, const int64_t *off,
                         const int32_t *chunk_c, const int64_t *chunk_b, int64_t n_chunks,
                         const PlanDev &pl, const LevelLists &ll, int64_t *t_min, int64_t *t_max,
@@ -358,8 +374,8 @@ hipError_t launch_correct(const State &st, const Params &pr, const int32_t *i_li
 hipError_t launch_init_finish(const State &st, const Params &pr, const double *acc_new,
                               const double *jerk_new, int64_t stride, DevCtl *ctl,
                               hipStream_t s);
-hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, double *pos, double *vel,
-                                 hipStream_t s);
+hipError_t launch_read_predicted(const Params &pr, const JBuf &jb, const int32_t *cid,
+                                 double *pos, double *vel, hipStream_t s);
 hipError_t launch_mirror(const DevCtl *ctl, HostMirror *mirror_dev, hipStream_t s);
 
 // ---- force (kernels_force.hip) --------------------------------------------

@@ -42,10 +42,11 @@ constexpr int64_t kOffJ3 = kOffJ2 + align256(16 * kMaxJ);      // V (float4) or 
 constexpr int64_t kOffHint = kOffJ3 + align256(16 * kMaxJ);    // 6 x kMaxJ doubles (a, jerk)
 constexpr int64_t kOffPart = kOffHint + align256(6 * 8 * kMaxJ);
 constexpr int64_t kOffSmall = kOffPart + align256(7 * 8 * kPartSlots);
-// small region: cluster offsets, scales, plan, control block
+// small region: cluster offsets, scales, bounding box, plan, control block
 constexpr int64_t kOffOff = kOffSmall;                    // int64[2]
 constexpr int64_t kOffScale = kOffOff + 256;              // float4 (as 4 x uint32 for atomics)
-constexpr int64_t kOffPlan = kOffScale + 256;             // plan arrays, 64 B each
+constexpr int64_t kOffBox = kOffScale + 256;              // 6 x uint64 ordered keys, double4 origin
+constexpr int64_t kOffPlan = kOffBox + 256;               // plan arrays, 64 B each
 constexpr int64_t kOffCtl = kOffPlan + 8 * 64;            // DevCtl
 constexpr int64_t kScratchBytes = align256(kOffCtl + (int64_t)sizeof(DevCtl));
 
@@ -84,8 +85,19 @@ unsigned char *scratch_ptr(int dev, int *cus, hipError_t *err) {
 
 // ---- kernels ----------------------------------------------------------------
 
-// Reset the control block, the cluster offsets and the scale accumulators.
-__global__ void k_static_clear(DevCtl *ctl, int64_t *off, unsigned *scale, int64_t n_j) {
+// Order-preserving integer keys of finite doubles (for atomic min / max).
+__device__ inline unsigned long long order_key(double x) {
+    const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+    return (u >> 63) ? ~u : (u | (1ull << 63));
+}
+__device__ inline double from_order_key(unsigned long long k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & ~(1ull << 63)) : ~k));
+}
+
+// Reset the control block, the cluster offsets, the scale accumulators and
+// the bounding box.
+__global__ void k_static_clear(DevCtl *ctl, int64_t *off, unsigned *scale,
+                               unsigned long long *box, int64_t n_j) {
     const int t = threadIdx.x;
     unsigned *c = reinterpret_cast<unsigned *>(ctl);
     for (int q = t; q < (int)(sizeof(DevCtl) / 4); q += blockDim.x)
@@ -99,6 +111,37 @@ __global__ void k_static_clear(DevCtl *ctl, int64_t *off, unsigned *scale, int64
         scale[2] = 0u;            // largest speed
         scale[3] = 0u;
     }
+    if (t < 3) {
+        box[t] = ~0ull;      // smallest coordinate on axis t
+        box[3 + t] = 0ull;   // largest
+    }
+}
+
+// Mixed form: the bounding box of the finite positions, whose centre rounded
+// to a multiple of 64 is the origin of the j-records (as a context's cluster).
+__global__ __launch_bounds__(kWG) void k_static_bounds(State st, int64_t n,
+                                                       unsigned long long *box) {
+    unsigned long long lo[3] = {~0ull, ~0ull, ~0ull}, hi[3] = {0ull, 0ull, 0ull};
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x) {
+        const double x[3] = {st.x[i], st.y[i], st.z[i]};
+        for (int q = 0; q < 3; q++)
+            if (isfinite(x[q])) {
+                const unsigned long long k = order_key(x[q]);
+                lo[q] = min(lo[q], k);
+                hi[q] = max(hi[q], k);
+            }
+    }
+    for (int q = 0; q < 3; q++)
+        for (int o = 32; o > 0; o >>= 1) {
+            lo[q] = min(lo[q], (unsigned long long)__shfl_xor((long long)lo[q], o));
+            hi[q] = max(hi[q], (unsigned long long)__shfl_xor((long long)hi[q], o));
+        }
+    if ((threadIdx.x & 63) == 0)
+        for (int q = 0; q < 3; q++) {
+            atomicMin(&box[q], lo[q]);
+            atomicMax(&box[3 + q], hi[q]);
+        }
 }
 
 __device__ inline float wave_max_f(float v) {
@@ -117,8 +160,18 @@ __device__ inline float wave_min_f(float v) {
 // smallest mass and largest speed, which size the near field.
 template <int MIXED>
 __global__ __launch_bounds__(kWG) void k_static_stage(State st, int64_t n, JBuf jb, double grid_q,
-                                                      double grid_inv, unsigned *scale) {
+                                                      double grid_inv, unsigned *scale,
+                                                      const unsigned long long *box,
+                                                      double4 *origin_out) {
     float mx = 0.f, mn = INFINITY, vx = 0.f;
+    double o[3] = {0.0, 0.0, 0.0};
+    if (MIXED)
+        for (int q = 0; q < 3; q++)
+            if (box[q] <= box[3 + q])  // some finite coordinate
+                o[q] = 64.0 * rint((0.5 * from_order_key(box[q]) +
+                                    0.5 * from_order_key(box[3 + q])) * (1.0 / 64.0));
+    if (MIXED && blockIdx.x == 0 && threadIdx.x == 0)
+        *origin_out = make_double4(o[0], o[1], o[2], 0.0);
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
         const double x = st.x[i], y = st.y[i], z = st.z[i];
@@ -127,7 +180,7 @@ __global__ __launch_bounds__(kWG) void k_static_stage(State st, int64_t n, JBuf 
         if (MIXED) {
             float4 P, Q, V;
             float2 R;
-            split_mixed(x, y, z, u, v, w, m, grid_q, grid_inv, P, Q, R, V);
+            split_mixed(x - o[0], y - o[1], z - o[2], u, v, w, m, grid_q, grid_inv, P, Q, R, V);
             jb.P[i] = P;
             jb.Q[i] = Q;
             jb.R[i] = R;
@@ -296,6 +349,8 @@ extern "C" int nbody_force_jerk_static(const nbody_direct *in, const int32_t *i_
     double *part = reinterpret_cast<double *>(base + kOffPart);
     int64_t *off = reinterpret_cast<int64_t *>(base + kOffOff);
     unsigned *scale = reinterpret_cast<unsigned *>(base + kOffScale);
+    unsigned long long *box = reinterpret_cast<unsigned long long *>(base + kOffBox);
+    double4 *origin = reinterpret_cast<double4 *>(base + kOffBox + 64);
     DevCtl *ctl = reinterpret_cast<DevCtl *>(base + kOffCtl);
     unsigned char *pb = base + kOffPlan;
     PlanDev pl{};
@@ -317,15 +372,19 @@ extern "C" int nbody_force_jerk_static(const nbody_direct *in, const int32_t *i_
     st.vz = const_cast<double *>(in->vel[2]);
     st.m = const_cast<double *>(in->mass);
 
-    hipLaunchKernelGGL(k_static_clear, dim3(1), dim3(64), 0, s, ctl, off, scale, N);
+    hipLaunchKernelGGL(k_static_clear, dim3(1), dim3(64), 0, s, ctl, off, scale, box, N);
     if ((e = hipGetLastError()) != hipSuccess)
         return NBODY_EDEVICE;
-    if (mixed)
+    if (mixed) {
+        hipLaunchKernelGGL(k_static_bounds, dim3(grid_for_n(N)), dim3(kWG), 0, s, st, N, box);
+        if ((e = hipGetLastError()) != hipSuccess)
+            return NBODY_EDEVICE;
         hipLaunchKernelGGL(k_static_stage<1>, dim3(grid_for_n(N)), dim3(kWG), 0, s, st, N, jb,
-                           grid_q, grid_inv, scale);
-    else
+                           grid_q, grid_inv, scale, box, origin);
+    } else {
         hipLaunchKernelGGL(k_static_stage<0>, dim3(grid_for_n(N)), dim3(kWG), 0, s, st, N, jb,
-                           grid_q, grid_inv, scale);
+                           grid_q, grid_inv, scale, box, origin);
+    }
     if ((e = hipGetLastError()) != hipSuccess)
         return NBODY_EDEVICE;
 
@@ -362,6 +421,7 @@ extern "C" int nbody_force_jerk_static(const nbody_direct *in, const int32_t *i_
     fa.tick = 1.0;
     fa.grid_q = grid_q;
     fa.grid_inv = grid_inv;
+    fa.origin = origin;
     fa.near_frac = 0.f;
     fa.near_frac_jerk = 0.f;
 

@@ -24,13 +24,21 @@ def _system(kind):
     if kind == "ensemble":
         x, v, m, offs = ensemble(6, 1012, 256, 1024)
         return x, v, m, offs
+    if kind == "shifted":
+        # clusters far from the coordinate origin: the mixed records' origins
+        # come from the checkpoint (the fresh context's positions are zero)
+        x, v, m, offs = ensemble(6, 1013, 256, 1024)
+        for k in range(6):
+            x[offs[k]:offs[k + 1]] += [1000.0 * (k - 2), -700.0 * k, 64.0 * k + 5]
+        return x, v, m, offs
     x, v, m = plummer(2000, 1010)
     return x, v, m, None
 
 
 @pytest.mark.parametrize("kind,prec", [("single", NBODY_PREC_FP64), ("single", NBODY_PREC_MIXED),
-                                       ("ensemble", NBODY_PREC_MIXED)],
-                         ids=["single-fp64", "single-mixed", "ensemble-mixed"])
+                                       ("ensemble", NBODY_PREC_MIXED),
+                                       ("shifted", NBODY_PREC_MIXED)],
+                         ids=["single-fp64", "single-mixed", "ensemble-mixed", "shifted-mixed"])
 def test_resume_is_bitwise_identical(tmp_path, kind, prec):
     note(f"checkpoint resume {kind} prec={prec}")
     x, v, m, offs = _system(kind)

@@ -694,6 +694,36 @@ def test_error_paths():
     g.close()
 
 
+def test_duplicate_in_correct_list_is_reported():
+    # a particle listed twice in one correction is corrected once and the
+    # next synchronising call reports ESTATE
+    note("duplicate index in nbody_correct")
+    x, v, m = plummer(600, 1008)
+    kw = dict(dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_FP64)
+    ref = NBody(x, v, m, 1 / 256, **kw)
+    dup = NBody(x, v, m, 1 / 256, **kw)
+    ref.init()
+    dup.init()
+    _, _, _, _, tg, dtg = ref.host_state()
+    t, act = _due(tg, dtg)
+    lst = np.concatenate([act, act[:1]]).astype(np.int32)
+    for g, il in ((ref, act), (dup, lst)):
+        g.predict(t)
+        acc, jerk, _ = g.force_jerk(il, t)
+        g.correct(il, t, acc, jerk)
+    ref.sync()
+    with pytest.raises(NBodyError) as e:
+        dup.sync()
+    assert e.value.code == _lib.NBODY_ESTATE
+    dup.sync()  # cleared
+    a, b = ref.host_state(), dup.host_state()
+    assert np.array_equal(a[4], b[4]) and np.array_equal(a[5], b[5])  # times, steps
+    for r, d in zip(a[:4], b[:4]):
+        assert np.abs(r - d).max() <= 1e-12 * (1 + np.abs(r).max())
+    ref.close()
+    dup.close()
+
+
 def test_block_steps_reject_unsynchronised_state():
     # Correcting only part of a due block leaves a state no block step can
     # continue from; so does a last time that is not a multiple of the step.
