@@ -591,6 +591,8 @@ def main():
                          "prediction pass, this many times each")
     ap.add_argument("--salpeter", type=int, default=196608,
                     help="a Salpeter-mass Plummer sphere of this N (0 = skip)")
+    ap.add_argument("--class-probes", type=str, default="",
+                    help="autotuner block sizes, one per size class (comma separated)")
     ap.add_argument("--quick", action="store_true",
                     help="the headline workload only (no block sizes, ensemble, Salpeter, "
                          "performance model)")
@@ -601,6 +603,9 @@ def main():
                     help="only time this many full sweeps, then one 512 MiB elementwise "
                          "copy of known size (for hardware-counter runs); prints one JSON line")
     args = ap.parse_args()
+    if args.class_probes:
+        global CLASS_PROBES
+        CLASS_PROBES = tuple(int(q) for q in args.class_probes.split(","))
     if args.quick:
         args.blocksizes = args.ensemble = args.salpeter = 0
         args.perfmodel = ""

@@ -166,7 +166,8 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
 
     __shared__ int64_t s_item;
     // the plan picks one class; a launch serves every class sharing its shape
-    const int cls_now = uniform_i32(*fa.cls);
+    const bool hplan = fa.host_plan != 0;  // a single cluster planned on the host
+    const int cls_now = hplan ? fa.hp.cls : uniform_i32(*fa.cls);
     if (((fa.cls_mask >> cls_now) & 1) == 0)
         return;
     if (FUSE)
@@ -187,7 +188,7 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
             }
         }
     }
-    const int64_t total = uniform_i64(*fa.total_items);
+    const int64_t total = hplan ? fa.hp.items : uniform_i64(*fa.total_items);
     // first round static (item = workgroup index); only when there are more
     // items than workgroups do finished workgroups pop further items from the
     // queue (items gridDim.x, gridDim.x+1, ...).  Small launches thus take no
@@ -211,18 +212,17 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
             c = lo;
         }
         c = uniform_i32(c);
-        const int64_t local = item - uniform_i64(fa.item_begin[c]);
-        const int S = uniform_i32(fa.S[c]);
+        const int64_t local = hplan ? item : item - uniform_i64(fa.item_begin[c]);
+        const int S = hplan ? fa.hp.S : uniform_i32(fa.S[c]);
         // slice-major order: consecutive items share a j-slice, so workgroups on
         // all eight XCDs work on the same slice at once and each XCD's L2 fetches
         // it about once instead of once per i-block
-        const int64_t n_c_items = uniform_i32(fa.n_cur[c]);
-        const int64_t nib_c = (n_c_items + IB - 1) / IB;
+        const int64_t n_c = hplan ? (int64_t)fa.hp_n : uniform_i32(fa.n_cur[c]);
+        const int64_t nib_c = (n_c + IB - 1) / IB;
         const int js = (int)(local / nib_c);
         const int64_t ib = local - (int64_t)js * nib_c;
-        const int64_t n_c = uniform_i32(fa.n_cur[c]);
         const int64_t cb = uniform_i64(fa.off[c]), ce = uniform_i64(fa.off[c + 1]);
-        const int64_t jl = uniform_i32(fa.jlen[c]);
+        const int64_t jl = hplan ? (int64_t)fa.hp.jl : uniform_i32(fa.jlen[c]);
         const int64_t j0 = cb + (int64_t)js * jl;
         const int64_t j1 = min(ce, j0 + jl);
         const int64_t slot0 = fa.slots_at_offsets ? cb : 0;
@@ -644,7 +644,7 @@ __device__ __forceinline__ void force_body(const ForceArgs &fa) {
                     if (POT)
                         fa.out_pot[o] = pot;
                 } else {
-                    const int64_t o = fa.part_begin[c] + (int64_t)js * n_c + kk[ii];
+                    const int64_t o = (hplan ? 0 : fa.part_begin[c]) + (int64_t)js * n_c + kk[ii];
                     const int64_t cap = fa.part_cap;
                     fa.part[o] = acc[ii].ax;
                     fa.part[cap + o] = acc[ii].ay;
@@ -681,7 +681,7 @@ __global__ __launch_bounds__(kWG, (ForceOcc<I, LJ, MIXED>::kMinBlocks)) void k_f
 // for that).
 template <int JT, bool MIXED, bool POT, bool EXCL, bool PM, bool FUSE>
 __global__ __launch_bounds__(kWG) void k_force_groups(ForceArgs fa) {
-    const int cls = uniform_i32(*fa.cls);
+    const int cls = fa.host_plan ? fa.hp.cls : uniform_i32(*fa.cls);
     if (((fa.cls_mask >> cls) & 1) == 0)
         return;
     switch ((fa.cls_lj >> (4 * cls)) & 15u) {

@@ -592,55 +592,25 @@ __device__ inline void plan_single_wave(const int64_t *off, const PlanDev &pl, D
                                         int64_t tcur, int32_t count_stats) {
     const int lane = threadIdx.x & 63;
     const int64_t Nc = off[1] - off[0];
-    int cls = kClasses - 1;
-    for (int k = 0; k < kClasses; k++)
-        if (n >= ct.min_n[k]) {
-            cls = k;
-            break;
-        }
+    const int cls = plan_class(ct, n);
     const int64_t ib_size = ct.ib[cls];
     const int64_t grid_res = ct.grid[cls];
     const int64_t j_tile = ct.jt[cls];
     const int64_t tiles = (Nc + j_tile - 1) / j_tile;
     const int64_t nib = (n + ib_size - 1) / ib_size;
     const int64_t grid = plan_grid(grid_res, nib, tiles);
-    // every candidate S in 32-bit integers (tiles < 2^23 for any cluster the
-    // ABI allows, S <= kMaxSlices) and waves = ceil(nib*Seff/grid) in FP64
-    // (exact: the product is below 2^53, and a quotient that is not an
-    // integer lies at least 1/grid from one): software 64-bit divisions made
-    // this loop the longest part of a small block step's first kernel
     const uint32_t tiles32 = (uint32_t)tiles;
     const double nibd = (double)nib, inv_grid = 1.0 / (double)grid;
     int64_t key = INT64_MAX;
     for (uint32_t S = lane + 1; S <= (uint32_t)kMaxSlices && S <= tiles32; S += 64) {
-        if (n <= 0 || (S > 1 && (int64_t)S * n > part_cap))
-            continue;
-        const uint32_t tps = (tiles32 + S - 1) / S;
-        const uint32_t Seff = (tiles32 + tps - 1) / tps;
-        const double q = nibd * (double)Seff;
-        double wv = ceil(q * inv_grid);
-        // the reciprocal product may round across an integer: step to the
-        // exact ceiling
-        if ((wv - 1.0) * (double)grid >= q)
-            wv -= 1.0;
-        else if (wv * (double)grid < q)
-            wv += 1.0;
-        const int64_t waves = (int64_t)wv;
-        const int64_t k2 = ((waves * (int64_t)(tps + 1)) << 11) | (int64_t)(S - 1);
+        const int64_t k2 = plan_key(S, tiles32, nibd, inv_grid, grid, n, part_cap);
         key = k2 < key ? k2 : key;
     }
     key = wave_min_i64(key);
     if (lane == 0) {
-        const int64_t S = key == INT64_MAX ? 1 : (key & 2047) + 1;
-        int64_t items = 0, parts = 0;
-        int32_t jl = 0, Sfin = 0;
-        if (n > 0 && Nc > 0) {
-            const int64_t tiles_per = (tiles + S - 1) / S;
-            jl = (int32_t)(tiles_per * j_tile);
-            Sfin = (int32_t)((Nc + jl - 1) / jl);
-            items = nib * Sfin;
-            parts = Sfin > 1 ? (int64_t)Sfin * n : 0;
-        }
+        const PlanChoice pc = plan_from_key(key, cls, n, Nc, tiles, j_tile, nib);
+        const int64_t items = pc.items, parts = pc.parts;
+        const int32_t jl = pc.jl, Sfin = pc.S;
         pl.n_cur[0] = (int32_t)n;
         pl.t_cur[0] = tcur;
         pl.S[0] = Sfin;
@@ -915,9 +885,19 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
     __shared__ int32_t s_si[kStage], s_sr[kStage];
     __shared__ int32_t s_lcnt[kLevels], s_lbase[kLevels];
     __shared__ int32_t s_ns;
-    const int smax = uniform_i32(*s_max);
+    // the force kernel's work queue back to zero: every evaluation ends here,
+    // so the next one finds it empty whether a plan kernel resets it (device
+    // plans) or not (plans made on the host)
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *fa.item_counter = 0;
+    const bool hplan = fa.host_plan != 0;  // plan values from the host
+    const int smax = hplan ? (fa.hp.S > 1 ? fa.hp.S : 0) : uniform_i32(*s_max);
     if (!CORR && smax <= 1)
         return;
+    // cluster c's block size, j-split and first partial-sum slot
+    auto plan_n = [&](int c) -> int64_t { return hplan ? (int64_t)fa.hp_n : fa.n_cur[c]; };
+    auto plan_S = [&](int c) -> int { return hplan ? fa.hp.S : fa.S[c]; };
+    auto plan_pb = [&](int c) -> int64_t { return hplan ? 0 : fa.part_begin[c]; };
     if (CORR) {
         if (threadIdx.x < kLevels) {
             dlev[threadIdx.x] = 0;
@@ -987,7 +967,7 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
     };
     int64_t bound = slot_space;
     if (fa.C == 1)
-        bound = min(bound, (int64_t)uniform_i32(fa.n_cur[0]));
+        bound = min(bound, uniform_i64(plan_n(0)));
     int64_t n_tot = -1;  // active slots of the plan, where known
     if (fa.C == 1)
         n_tot = bound;
@@ -1008,15 +988,15 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
             if (s < bound) {
                 c = fa.C > 1 ? cid[s] : 0;
                 k = fa.slots_at_offsets ? s - fa.off[c] : s;
-                n = fa.n_cur[c];
-                S = fa.S[c];
+                n = plan_n(c);
+                S = plan_S(c);
                 live = k < n && (CORR || S > 1);
             }
             double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if (live && S > 1) {
                 const int per = (S + 3) >> 2;
                 const int j0 = w * per, j1 = min(S, j0 + per);
-                const int64_t base = fa.part_begin[c] + k;
+                const int64_t base = plan_pb(c) + k;
                 for (int js = j0; js < j1; js++) {
 #pragma unroll
                     for (int q = 0; q < 7; q++)
@@ -1055,8 +1035,8 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
         for (int64_t s = blockIdx.x; s < bound; s += gridDim.x) {
             const int c = fa.C > 1 ? uniform_i32(cid[s]) : 0;
             const int64_t k = fa.slots_at_offsets ? s - uniform_i64(fa.off[c]) : s;
-            const int64_t n = uniform_i32(fa.n_cur[c]);
-            const int S = uniform_i32(fa.S[c]);
+            const int64_t n = uniform_i64(plan_n(c));
+            const int S = uniform_i32(plan_S(c));
             if (k >= n)
                 continue;
             if (S <= 1) {
@@ -1077,7 +1057,7 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                 }
                 continue;
             }
-            const int64_t base = uniform_i64(fa.part_begin[c]) + k;
+            const int64_t base = uniform_i64(plan_pb(c)) + k;
             // all seven components' loads of a slice together, then the sums
             double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             for (int js = t; js < S; js += kWG) {
@@ -1128,13 +1108,13 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
             if (s < bound) {
                 c = fa.C > 1 ? cid[s] : 0;
                 k = fa.slots_at_offsets ? s - fa.off[c] : s;
-                n = fa.n_cur[c];
-                S = fa.S[c];
+                n = plan_n(c);
+                S = plan_S(c);
                 live = k < n && (CORR || S > 1);
             }
             double v[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if (live && S > 1) {
-                const int64_t base = fa.part_begin[c] + k;
+                const int64_t base = plan_pb(c) + k;
                 for (int js = l; js < S; js += L) {
 #pragma unroll
                     for (int q = 0; q < 7; q++)

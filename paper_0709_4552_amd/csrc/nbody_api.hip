@@ -251,13 +251,23 @@ hipError_t enqueue_force(nbody_ctx *c, const int32_t *i_list, int slots_at_offse
     const int mixed = c->pr.precision == NBODY_PREC_MIXED;
     const ClassTable ct = class_table(c, want_pot, excl);
     int only = -1;
-    if (host_n >= 0)
-        only = class_of(c, host_n);
-    hipError_t e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl,
-                               c->part_cap, ct, host_n, host_t, count_stats, c->stream);
-    if (e != hipSuccess)
-        return e;
     ForceArgs fa = force_args(c, i_list, slots_at_offsets, acc, jerk, pot, stride);
+    hipError_t e = hipSuccess;
+    if (host_n >= 0 && c->pr.C == 1 && !count_stats) {
+        // one cluster, n known here: plan on the host, launch only that
+        // class's kernel, no plan kernel
+        fa.host_plan = 1;
+        fa.hp = plan_on_host(ct, host_n, c->pr.n_total, c->part_cap);
+        fa.hp_n = host_n;
+        only = fa.hp.cls;
+    } else {
+        if (host_n >= 0)
+            only = class_of(c, host_n);
+        e = launch_plan(c->pr, c->off_d, c->pl, c->n_act_d, c->t_next_d, c->ctl, c->part_cap,
+                        ct, host_n, host_t, count_stats, c->stream);
+        if (e != hipSuccess)
+            return e;
+    }
     e = launch_classes(c, fa, mixed, want_pot, excl, only);
     if (e != hipSuccess)
         return e;

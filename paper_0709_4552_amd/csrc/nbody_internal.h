@@ -74,6 +74,82 @@ struct ClassTable {
     int32_t jt[kClasses];     // j-slice granularity of the class's shape
 };
 
+// The plan of one evaluation of n of a single cluster's Nc particles: the
+// shape class, the j-split S (slices of jl j-particles), and the work items
+// and partial-sum slots that needs.  Candidate splits S = 1..kMaxSlices are
+// ranked by plan_key (waves of items over the planning grid, then slice
+// length, then S); the device planner ranks them across the lanes of a wave,
+// the host (evaluations whose n it knows) in a loop: both take the same
+// minimum, so both choose the same plan.
+struct PlanChoice {
+    int32_t cls, S, jl;
+    int64_t items, parts;
+};
+
+__host__ __device__ inline int plan_class(const ClassTable &ct, int64_t n) {
+    for (int k = 0; k < kClasses; k++)
+        if (n >= ct.min_n[k])
+            return k;
+    return kClasses - 1;
+}
+
+// Rank of j-split S (INT64_MAX: not allowed).  Arithmetic in 32-bit integers
+// (tiles < 2^23 for any cluster the ABI allows, S <= kMaxSlices) and
+// waves = ceil(nib*Seff/grid) in FP64 (exact: the product is below 2^53, and a
+// quotient that is not an integer lies at least 1/grid from one): software
+// 64-bit divisions made the device loop the longest part of a small block
+// step's first kernel.
+__host__ __device__ inline int64_t plan_key(uint32_t S, uint32_t tiles32, double nibd,
+                                            double inv_grid, int64_t grid, int64_t n,
+                                            int64_t part_cap) {
+    if (n <= 0 || (S > 1 && (int64_t)S * n > part_cap))
+        return INT64_MAX;
+    const uint32_t tps = (tiles32 + S - 1) / S;
+    const uint32_t Seff = (tiles32 + tps - 1) / tps;
+    const double q = nibd * (double)Seff;
+    double wv = ceil(q * inv_grid);
+    // the reciprocal product may round across an integer: step to the exact
+    // ceiling
+    if ((wv - 1.0) * (double)grid >= q)
+        wv -= 1.0;
+    else if (wv * (double)grid < q)
+        wv += 1.0;
+    const int64_t waves = (int64_t)wv;
+    return ((waves * (int64_t)(tps + 1)) << 11) | (int64_t)(S - 1);
+}
+
+// The plan from the best key (INT64_MAX: S = 1).
+__host__ __device__ inline PlanChoice plan_from_key(int64_t key, int cls, int64_t n, int64_t Nc,
+                                                    int64_t tiles, int64_t j_tile, int64_t nib) {
+    PlanChoice p{cls, 0, 0, 0, 0};
+    const int64_t S = key == INT64_MAX ? 1 : (key & 2047) + 1;
+    if (n > 0 && Nc > 0) {
+        const int64_t tiles_per = (tiles + S - 1) / S;
+        p.jl = (int32_t)(tiles_per * j_tile);
+        p.S = (int32_t)((Nc + p.jl - 1) / p.jl);
+        p.items = nib * p.S;
+        p.parts = p.S > 1 ? (int64_t)p.S * n : 0;
+    }
+    return p;
+}
+
+// The same plan on the host: every candidate S in turn.
+inline PlanChoice plan_on_host(const ClassTable &ct, int64_t n, int64_t Nc, int64_t part_cap) {
+    const int cls = plan_class(ct, n);
+    const int64_t j_tile = ct.jt[cls];
+    const int64_t tiles = (Nc + j_tile - 1) / j_tile;
+    const int64_t nib = (n + ct.ib[cls] - 1) / ct.ib[cls];
+    const int64_t grid = plan_grid(ct.grid[cls], nib, tiles);
+    const uint32_t tiles32 = (uint32_t)tiles;
+    const double nibd = (double)nib, inv_grid = 1.0 / (double)grid;
+    int64_t key = INT64_MAX;
+    for (uint32_t S = 1; S <= (uint32_t)kMaxSlices && S <= tiles32; S++) {
+        const int64_t k2 = plan_key(S, tiles32, nibd, inv_grid, grid, n, part_cap);
+        key = k2 < key ? k2 : key;
+    }
+    return plan_from_key(key, cls, n, Nc, tiles, j_tile, nib);
+}
+
 // Predicted j-particle buffer.
 //  mixed: P = (x_hi, y_hi, z_hi, m), Q = (x_lo, y_lo, z_lo, vx), R = (vy, vz)
 //         with x_hi = q rint(x/q) on the fixed grid q (so x_hi_j - x_hi_i is
@@ -214,6 +290,11 @@ struct ForceArgs {
     const int64_t *t_cur;
     double tick, grid_q, grid_inv;
     const double4 *origin;          // the cluster's origin (in-kernel prediction)
+    // a plan made on the host (one cluster, n known there): the force and
+    // reduction kernels take it from here instead of the plan arrays
+    int32_t host_plan;
+    PlanChoice hp;
+    int32_t hp_n;
 };
 
 // Third-order Taylor prediction of particle i to tick T (section 4.1, step

@@ -249,10 +249,10 @@ const Shape kShapes[kClasses] = {{1, 1, 256}, {1, 4, 256}, {1, 16, 256}, {1, 64,
                                  {1, 256, 256}};
 const int32_t kMinN[kClasses] = {2048, 256, 32, 4, 0};
 
-// One force evaluation: plan (one wave), the force launches of the classes
-// (the one-lane shape and the shared lane-group launch), j-split reduction.
-hipError_t evaluate(ForceArgs fa, const PlanDev &pl, DevCtl *ctl, int mixed, int want_pot,
-                    int excl, int cus, int64_t n, hipStream_t s) {
+// One force evaluation: the plan (made here), the planned class's force
+// launch (the one-lane shape or the lane-group launch), j-split reduction.
+hipError_t evaluate(ForceArgs fa, DevCtl *ctl, int mixed, int want_pot, int excl, int cus,
+                    int64_t n, hipStream_t s) {
     const int pm = mixed;  // the per-pair near test: masses are not known on the host
     ClassTable ct{};
     int grid[kClasses];
@@ -264,13 +264,10 @@ hipError_t evaluate(ForceArgs fa, const PlanDev &pl, DevCtl *ctl, int mixed, int
         ct.grid[k] = grid[k];
         ct.jt[k] = force_j_step(kShapes[k]);
     }
-    Params pr{};
-    pr.n_total = fa.n_total;
-    pr.C = 1;
-    hipError_t e = launch_plan(pr, fa.off, pl, nullptr, nullptr, ctl, fa.part_cap, ct, (int32_t)n,
-                               0, 0, s);
-    if (e != hipSuccess)
-        return e;
+    // the plan, made here: only the planned class's kernel is launched
+    fa.host_plan = 1;
+    fa.hp = plan_on_host(ct, n, fa.n_total, fa.part_cap);
+    fa.hp_n = (int32_t)n;
     fa.cls_lj = 0;
     for (int k = 0; k < kClasses; k++) {
         int lg = 0;
@@ -278,12 +275,11 @@ hipError_t evaluate(ForceArgs fa, const PlanDev &pl, DevCtl *ctl, int mixed, int
             lg++;
         fa.cls_lj |= (uint32_t)lg << (4 * k);
     }
-    // class 0 alone (one lane per i); classes 1-4 share the lane-group launch
-    fa.cls_mask = 1;
-    if ((e = launch_force(kShapes[0], mixed, want_pot, excl, pm, fa, grid[0], s)) != hipSuccess)
-        return e;
-    fa.cls_mask = 0x1e;
-    if ((e = launch_force(kShapes[1], mixed, want_pot, excl, pm, fa, grid[1], s)) != hipSuccess)
+    // class 0: one lane per i; classes 1-4: the lane-group launch
+    const int k = fa.hp.cls;
+    fa.cls_mask = 1 << k;
+    hipError_t e = launch_force(kShapes[k], mixed, want_pot, excl, pm, fa, grid[k], s);
+    if (e != hipSuccess)
         return e;
     return launch_reduce(fa, nullptr, n, &ctl->s_max, s);
 }
@@ -438,7 +434,7 @@ extern "C" int nbody_force_jerk_static(const nbody_direct *in, const int32_t *i_
             fa.hax = fa.hay = fa.haz = nullptr;
             fa.hjx = fa.hjy = fa.hjz = nullptr;
             fa.out_pot = nullptr;
-            if ((e = evaluate(fa, pl, ctl, mixed, 0, excl, cus, n, s)) != hipSuccess)
+            if ((e = evaluate(fa, ctl, mixed, 0, excl, cus, n, s)) != hipSuccess)
                 return NBODY_EDEVICE;
             hipLaunchKernelGGL(k_static_hints, dim3(grid_for_n(n)), dim3(kWG), 0, s, i_list, n, N,
                                acc, jerk, hint);
@@ -459,7 +455,7 @@ extern "C" int nbody_force_jerk_static(const nbody_direct *in, const int32_t *i_
         fa.near_frac = kNearFrac;
         fa.near_frac_jerk = kNearFracJerk;
     }
-    if ((e = evaluate(fa, pl, ctl, mixed, want_pot, excl, cus, n, s)) != hipSuccess)
+    if ((e = evaluate(fa, ctl, mixed, want_pot, excl, cus, n, s)) != hipSuccess)
         return NBODY_EDEVICE;
     return NBODY_OK;
 }

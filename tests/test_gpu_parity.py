@@ -724,6 +724,41 @@ def test_duplicate_in_correct_list_is_reported():
     dup.close()
 
 
+def test_explicit_steps_equal_block_steps_bitwise():
+    # Explicit evaluations are planned on the host, block steps on the device,
+    # by the same rules: in FP64 each particle's sums follow only the plan
+    # (class, j-split, slice length), so explicit predict / force / correct of
+    # each due block must reproduce the block steps bit for bit.
+    note("explicit steps (host plan) against block steps (device plan), fp64")
+    x, v, m = plummer(2500, 1009)
+    kw = dict(dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_FP64)
+    a = NBody(x, v, m, 1 / 256, **kw)
+    b = NBody(x, v, m, 1 / 256, **kw)
+    a.init()
+    b.init()
+    # the start-up sweep (n = N, device plan) against an explicit one
+    _, _, a0, j0, _, _ = a.host_state()
+    b.predict(0.0)
+    acc, jerk, _ = b.force_jerk(np.arange(2500, dtype=np.int32), 0.0, want_pot=False)
+    assert np.array_equal(acc.T.cpu().numpy(), a0) and np.array_equal(jerk.T.cpu().numpy(), j0)
+    sizes = []
+    for _ in range(60):
+        t, n = a.step_block(True)
+        _, _, _, _, tg, dtg = b.host_state()
+        tb, act = _due(tg, dtg)
+        assert tb == t and len(act) == n
+        sizes.append(n)
+        b.predict(tb)
+        acc, jerk, _ = b.force_jerk(act, tb, want_pot=False)  # as block steps
+        b.correct(act, tb, acc, jerk)
+    for r, g in zip(a.host_state(), b.host_state()):
+        assert np.array_equal(r, g)
+    note(f"  60 steps, block sizes {min(sizes)}..{max(sizes)}")
+    assert min(sizes) < 32 and max(sizes) >= 256  # several size classes
+    a.close()
+    b.close()
+
+
 def test_block_steps_reject_unsynchronised_state():
     # Correcting only part of a due block leaves a state no block step can
     # continue from; so does a last time that is not a multiple of the step.
