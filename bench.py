@@ -39,8 +39,8 @@ SEED = 1003
 # HBM traffic of the full-sweep kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE runs, scaled by the
 # same counters on an elementwise kernel of known size; valid only for the kernel source it was
 # measured on (checked by hash, else "traffic" is reported as null).
-SWEEP_TRAFFIC = {"force_source_sha256_prefix": "bfded5c04db0573d", "read_bytes": 140.3e6,
-                 "write_bytes": 66.2e6}
+SWEEP_TRAFFIC = {"force_source_sha256_prefix": "953190131d06b8a2", "read_bytes": 215.2e6,
+                 "write_bytes": 71.4e6}
 
 
 # Autotuner probe sizes, one per block-size class (n >= 2048, >= 256, >= 32,
