@@ -151,7 +151,9 @@ const char *nbody_strerror(int status);
 /*
  * Create a context for the given parameters and caller-owned state.
  * `stream` is a hipStream_t (NULL = the null stream).  Allocates the
- * context's device buffers (about 140 B per particle plus the work plan).
+ * context's device buffers: 124 + 8 * (dt_max_log2 - dt_min_log2 + 1) B per
+ * particle (j-particle records, results, active list, per-level lists), 56 B
+ * per partial-sum slot (clamp(8 N, 2^20, 2^24) slots) and the per-cluster plan.
  * The state is not read until nbody_init.
  * Errors: EINVAL (bad sizes, offsets, eps, eta, step range, precision or a
  * NULL state array), ENOMEM, EDEVICE.

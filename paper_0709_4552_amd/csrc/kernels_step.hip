@@ -1302,7 +1302,7 @@ hipError_t launch_plan(const Params &pr, const int64_t *off, const PlanDev &pl, 
                        int64_t *t_next, DevCtl *ctl, int64_t part_cap, const ClassTable &ct,
                        int32_t host_n, int64_t host_t, int32_t count_stats, hipStream_t s) {
     if (pr.C == 1) {
-        // a single cluster's block steps plan inside k_plan_predict_compact
+        // a single cluster's block steps plan inside k_plan_predict_gather
         if (host_n == kPlanFromLevels)
             return hipErrorInvalidValue;
         hipLaunchKernelGGL(k_plan_one, dim3(1), dim3(64), 0, s, pr, off, pl, n_act, t_next, ctl,
