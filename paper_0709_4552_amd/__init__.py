@@ -103,14 +103,28 @@ class NBody:
     def predict(self, t: float):
         check(_lib.nbody_predict(self.ctx, t), "nbody_predict")
 
-    def force_jerk(self, i_list, t: float, want_pot: bool = True):
-        """Returns (acc (3,n), jerk (3,n), pot (n,) or None) as device tensors."""
+    def force_jerk(self, i_list, t: float, want_pot: bool = True, out=None):
+        """Returns (acc (3,n), jerk (3,n), pot (n,) or None) as device tensors.
+
+        out: optional (acc, jerk, pot-or-None) float64 device tensors of those
+        shapes to write into (no allocation per call)."""
         torch = self.torch
         il = torch.as_tensor(i_list, dtype=torch.int32, device=self.dev).contiguous()
         n = il.numel()
-        acc = torch.empty((3, n), dtype=torch.float64, device=self.dev)
-        jerk = torch.empty((3, n), dtype=torch.float64, device=self.dev)
-        pot = torch.empty(n, dtype=torch.float64, device=self.dev) if want_pot else None
+        if out is not None:
+            acc, jerk, pot = out
+            if (tuple(acc.shape) != (3, n) or tuple(jerk.shape) != (3, n) or
+                    acc.dtype != torch.float64 or jerk.dtype != torch.float64 or
+                    not (acc.is_contiguous() and jerk.is_contiguous()) or
+                    (want_pot and (pot is None or tuple(pot.shape) != (n,) or
+                                   pot.dtype != torch.float64))):
+                raise ValueError("out must hold float64 (3, n), (3, n) and (n,) tensors")
+            if not want_pot:
+                pot = None
+        else:
+            acc = torch.empty((3, n), dtype=torch.float64, device=self.dev)
+            jerk = torch.empty((3, n), dtype=torch.float64, device=self.dev)
+            pot = torch.empty(n, dtype=torch.float64, device=self.dev) if want_pot else None
         check(_lib.nbody_force_jerk(self.ctx, il.data_ptr(), n, t, acc.data_ptr(),
                                     jerk.data_ptr(), pot.data_ptr() if want_pot else None),
               "nbody_force_jerk")

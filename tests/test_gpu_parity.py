@@ -113,6 +113,27 @@ def test_force_jerk_matches_oracle(prec, n):
     g.close()
 
 
+def test_force_jerk_into_caller_buffers():
+    # the same call writing into buffers the caller allocated once
+    x, v, m = plummer(1500, 1004)
+    g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g.init()
+    g.predict(0.0)
+    il = np.arange(0, 1500, 7, dtype=np.int32)
+    n = len(il)
+    ref = g.force_jerk(il, 0.0)
+    torch = g.torch
+    out = tuple(torch.full(s, np.nan, dtype=torch.float64, device=g.dev)
+                for s in ((3, n), (3, n), (n,)))
+    got = g.force_jerk(il, 0.0, out=out)
+    for r, o, b in zip(ref, got, out):
+        assert o.data_ptr() == b.data_ptr()
+        assert torch.equal(r, o)
+    with pytest.raises(ValueError):
+        g.force_jerk(il, 0.0, out=(out[0][:, :-1], out[1], out[2]))
+    g.close()
+
+
 @pytest.mark.parametrize("prec", PREC, ids=PID)
 def test_force_jerk_unequal_masses(prec):
     # Salpeter masses over 0.1-100: the near field of the mixed form is sized
