@@ -997,7 +997,23 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
                 const int per = (S + 3) >> 2;
                 const int j0 = w * per, j1 = min(S, j0 + per);
                 const int64_t base = plan_pb(c) + k;
-                for (int js = j0; js < j1; js++) {
+                // four slices' loads go out together, then their sums in slice
+                // order (the same order as one slice at a time)
+                int js = j0;
+                for (; js + 3 < j1; js += 4) {
+                    double u[4][7];
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int q = 0; q < 7; q++)
+                            u[r][q] = fa.part[q * fa.part_cap + base + (int64_t)(js + r) * n];
+#pragma unroll
+                    for (int r = 0; r < 4; r++)
+#pragma unroll
+                        for (int q = 0; q < 7; q++)
+                            v[q] += u[r][q];
+                }
+                for (; js < j1; js++) {
 #pragma unroll
                     for (int q = 0; q < 7; q++)
                         v[q] += fa.part[q * fa.part_cap + base + (int64_t)js * n];
