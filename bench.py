@@ -204,8 +204,11 @@ def blocksize_sweep(torch, n_big: int, cpu_check: bool):
     x, v, m = plummer(n_big, 1005)
     g = NBody(x, v, m, 1.0 / 4096, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
     g.init()
+    tuning = []
     for n_probe in (65536, 4096, 128, 16, 1):
-        g.autotune(min(n_probe, n_big))
+        t, ms = g.autotune(min(n_probe, n_big))
+        t["n_probe"], t["ms"] = min(n_probe, n_big), ms
+        tuning.append(t)
     g.predict(0.0)
     rng = np.random.Generator(np.random.PCG64(1006))
     out = []
@@ -251,7 +254,8 @@ def blocksize_sweep(torch, n_big: int, cpu_check: bool):
         out.append(rec)
         log(f"N={n_big} n={label}: {ms:.3f} ms {rate:.3e} int/s")
     g.close()
-    return {"workload": f"plummer_N{n_big}_eps1/4096_mixed_force_only", "points": out}
+    return {"workload": f"plummer_N{n_big}_eps1/4096_mixed_force_only", "autotuned_shapes": tuning,
+            "points": out}
 
 
 def ensemble_bench(torch, n_clusters: int, t_short: float, t_full: float, per_cluster: bool):

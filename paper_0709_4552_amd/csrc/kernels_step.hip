@@ -851,24 +851,31 @@ struct CorrArgs {
 __device__ inline void list_append(const CorrArgs &ca, const int64_t *off, int c, int nl,
                                    int64_t i) {
     const int lane = threadIdx.x & 63;
-    uint64_t pending = __ballot(nl >= 0);
+    const bool has = nl >= 0;
+    // group the lanes by (cluster, level) first (no memory access), so that the
+    // groups' leaders then reserve their places all at once
+    uint64_t pending = __ballot(has);
+    uint64_t mine = 0;
     while (pending) {
         const int leader = __ffsll((unsigned long long)pending) - 1;
         const int kc = __builtin_amdgcn_readlane(c, leader);
         const int kl = __builtin_amdgcn_readlane(nl, leader);
-        const uint64_t m = __ballot(nl >= 0 && c == kc && nl == kl) & pending;
-        int base = 0, tb = 0;
-        if (lane == leader) {
-            tb = ca.ll.buf[(int64_t)kc * kLevels + kl];
-            base = atomicAdd(list_cnt(ca.ll, tb, kc, kl), (int)__popcll(m));
-        }
-        base = __builtin_amdgcn_readlane(base, leader);
-        tb = __builtin_amdgcn_readlane(tb, leader);
-        if ((m >> lane) & 1ull) {
-            const int rank = (int)__popcll(m & ((1ull << lane) - 1ull));
-            list_at(ca.ll, tb, kl, off[kc])[base + rank] = (int32_t)i;
-        }
+        const uint64_t m = __ballot(has && c == kc && nl == kl) & pending;
+        if ((m >> lane) & 1ull)
+            mine = m;
         pending &= ~m;
+    }
+    const int leader = has ? __ffsll((unsigned long long)mine) - 1 : lane;
+    int base = 0, tb = 0;
+    if (has && lane == leader) {
+        tb = ca.ll.buf[(int64_t)c * kLevels + nl];
+        base = atomicAdd(list_cnt(ca.ll, tb, c, nl), (int)__popcll(mine));
+    }
+    base = __shfl(base, leader);
+    tb = __shfl(tb, leader);
+    if (has) {
+        const int rank = (int)__popcll(mine & ((1ull << lane) - 1ull));
+        list_at(ca.ll, tb, nl, off[c])[base + rank] = (int32_t)i;
     }
 }
 
