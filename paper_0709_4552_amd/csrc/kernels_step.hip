@@ -821,10 +821,12 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
 // most four slices, widened (up to S) while the slots times L come to fewer
 // than kReduceLanes lanes, so that small blocks still spread over the chip;
 // loads of one slice are consecutive over the slots.  Splits wider than 64
-// with no more slots than workgroups take a workgroup per slot instead (thread
-// t adds slices t, t+256, ..., then DPP trees and the four wave sums in
-// order).  Every order is fixed, so results are bitwise reproducible for a
-// given plan.  With one cluster only the n live slots are visited.
+// of blocks of at most kWgSlots slots take a workgroup per slot instead
+// (thread t adds slices t, t+256, ..., then DPP trees and the four wave sums in
+// order).  Every order is fixed and follows from the plan alone (never from the
+// launch's grid), so results are bitwise reproducible for a given plan, and an
+// explicit evaluation of a block sums it as the block step does.  With one
+// cluster only the n live slots are visited.
 //
 // CORR (a block step): instead of storing a slot's sums, correct its particle
 // with them right away (slots of clusters that were not split take the force
@@ -833,6 +835,7 @@ __global__ __launch_bounds__(kWG) void k_correct(State st, Params pr, const int3
 // cluster) or added to the cluster's row directly (several).
 constexpr int64_t kReduceLanes = 1 << 17;
 constexpr int64_t kTileMin = 256;  // blocks of at least this many slots use slot tiles
+constexpr int64_t kWgSlots = 1024;  // wide splits of blocks up to this size: a workgroup per slot
 
 struct CorrArgs {
     State st;
@@ -980,7 +983,7 @@ __global__ __launch_bounds__(kWG) void k_reduce_t(ForceArgs fa, const int32_t *c
         n_tot = bound;
     else if (CORR)
         n_tot = uniform_i32(ca.ctl->n_last);
-    const bool wg_mode = smax > 64 && (n_tot < 0 || n_tot <= (int64_t)gridDim.x);
+    const bool wg_mode = smax > 64 && (n_tot < 0 || n_tot <= kWgSlots);
     // Large split blocks: a workgroup takes 64 consecutive slots (lane = slot,
     // so a slice's loads are contiguous), wave w sums the slices of the w-th
     // quarter in order, and the quarters are added in wave order through LDS.
@@ -1356,9 +1359,9 @@ hipError_t launch_plan_predict_gather(const State &st, const Params &pr, const J
 hipError_t launch_reduce(const ForceArgs &fa, const int32_t *cid, int64_t slot_space,
                          const int32_t *s_max, hipStream_t s) {
     // enough waves for one per slot up to 4096 workgroups (grid-stride
-    // beyond), and a workgroup per slot up to 1024 slots, so wide splits of
-    // small blocks are summed a workgroup per slot
-    const int64_t g = std::max<int64_t>(grid_for(slot_space * 64), std::min<int64_t>(slot_space, 1024));
+    // beyond), and a workgroup per slot up to kWgSlots slots, so wide splits
+    // of small blocks are summed a workgroup per slot
+    const int64_t g = std::max<int64_t>(grid_for(slot_space * 64), std::min<int64_t>(slot_space, kWgSlots));
     hipLaunchKernelGGL(k_reduce_t<false>, dim3((unsigned)g), dim3(kWG), 0, s, fa,
                        cid, slot_space, s_max, CorrArgs{});
     return hipGetLastError();
@@ -1371,7 +1374,7 @@ hipError_t launch_reduce_correct(const ForceArgs &fa, const State &st, const Par
     // unsplit and narrow splits, grid-stride waves / workgroups for wider ones
     const int64_t n = pr.n_total;
     const int64_t g = std::min<int64_t>(4096, std::max<int64_t>((n + kWG - 1) / kWG,
-                                                                std::min<int64_t>(n, 1024)));
+                                                                std::min<int64_t>(n, kWgSlots)));
     const CorrArgs ca{st, pr, pl.t_cur, pl.t_now, pl.lev_cnt, ll, ctl};
     hipLaunchKernelGGL(k_reduce_t<true>, dim3((unsigned)g), dim3(kWG), 0, s, fa, cid, n, s_max,
                        ca);

@@ -745,13 +745,12 @@ def test_duplicate_in_correct_list_is_reported():
     dup.close()
 
 
-def test_explicit_steps_equal_block_steps_bitwise():
+def _explicit_against_block_steps(n_part, steps):
     # Explicit evaluations are planned on the host, block steps on the device,
     # by the same rules: in FP64 each particle's sums follow only the plan
     # (class, j-split, slice length), so explicit predict / force / correct of
     # each due block must reproduce the block steps bit for bit.
-    note("explicit steps (host plan) against block steps (device plan), fp64")
-    x, v, m = plummer(2500, 1009)
+    x, v, m = plummer(n_part, 1009)
     kw = dict(dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_FP64)
     a = NBody(x, v, m, 1 / 256, **kw)
     b = NBody(x, v, m, 1 / 256, **kw)
@@ -760,10 +759,10 @@ def test_explicit_steps_equal_block_steps_bitwise():
     # the start-up sweep (n = N, device plan) against an explicit one
     _, _, a0, j0, _, _ = a.host_state()
     b.predict(0.0)
-    acc, jerk, _ = b.force_jerk(np.arange(2500, dtype=np.int32), 0.0, want_pot=False)
+    acc, jerk, _ = b.force_jerk(np.arange(n_part, dtype=np.int32), 0.0, want_pot=False)
     assert np.array_equal(acc.T.cpu().numpy(), a0) and np.array_equal(jerk.T.cpu().numpy(), j0)
     sizes = []
-    for _ in range(60):
+    for _ in range(steps):
         t, n = a.step_block(True)
         _, _, _, _, tg, dtg = b.host_state()
         tb, act = _due(tg, dtg)
@@ -774,10 +773,25 @@ def test_explicit_steps_equal_block_steps_bitwise():
         b.correct(act, tb, acc, jerk)
     for r, g in zip(a.host_state(), b.host_state()):
         assert np.array_equal(r, g)
-    note(f"  60 steps, block sizes {min(sizes)}..{max(sizes)}")
-    assert min(sizes) < 32 and max(sizes) >= 256  # several size classes
+    note(f"  {steps} steps, block sizes {min(sizes)}..{max(sizes)}")
     a.close()
     b.close()
+    return sizes
+
+
+def test_explicit_steps_equal_block_steps_bitwise():
+    note("explicit steps (host plan) against block steps (device plan), fp64")
+    sizes = _explicit_against_block_steps(2500, 60)
+    assert min(sizes) < 32 and max(sizes) >= 256  # several size classes
+
+
+def test_explicit_steps_equal_block_steps_bitwise_large_n():
+    # Above 2^18 particles the block steps' reduction runs on more than 1024
+    # workgroups, explicit ones on 1024 for blocks of 1025-4096: the summation
+    # order of a split block must follow from its plan, not from the grid.
+    note("explicit steps against block steps at N = 2^19, fp64")
+    sizes = _explicit_against_block_steps(1 << 19, 16)
+    assert any(1024 < n <= 2048 for n in sizes)  # blocks the two grids would sum differently
 
 
 def test_block_steps_reject_unsynchronised_state():
