@@ -664,6 +664,60 @@ def test_tiny_clusters_and_ragged_sizes(prec):
 
 
 @pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_tiny_single_cluster_systems(prec):
+    # whole contexts of 1, 2 and 3 particles (not clusters of an ensemble):
+    # one particle moves in a straight line; two and three follow the oracle
+    note(f"single-cluster systems of 1-3 particles prec={prec}")
+    eps, T = 1 / 256, 1 / 16
+    kw = dict(dt_min_log2=-20, dt_max_log2=-6)
+    prm = oracle.params(eps, **kw)
+    for n in (1, 2, 3):
+        x, v, m = plummer(n, 2100 + n) if n > 1 else (
+            np.array([[0.3, -0.2, 0.1]]), np.array([[0.5, 0.25, -0.75]]), np.array([1.0]))
+        g = NBody(x, v, m, eps, precision=prec, **kw)
+        g.init()
+        g.run_until(T)
+        xg, vg, _, _, tg, _ = g.host_state()
+        assert np.all(tg == T), n
+        if n == 1:
+            np.testing.assert_allclose(xg[0], x[0] + T * v[0], rtol=0, atol=1e-15)
+            np.testing.assert_array_equal(vg[0], v[0])
+        else:
+            ref = oracle.System(x, v, m, prm)
+            ref.run(T)
+            tol = 1e-10 if prec == NBODY_PREC_FP64 else 1e-6
+            assert np.abs(xg - ref.x).max() <= tol, n
+        g.close()
+
+
+def test_empty_and_oversized_lists_and_no_op_run():
+    # 1 <= n <= n_total for the explicit calls (EINVAL otherwise, nothing
+    # enqueued); run_until to the current time steps nothing
+    note("empty / oversized lists, run_until(now)")
+    import torch
+    x, v, m = plummer(300, 1021)
+    g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g.init()
+    g.run_until(2.0 ** -5)
+    before = [q.clone() for q in (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)]
+    assert g.run_until(2.0 ** -5) == 0
+    g.predict(2.0 ** -5)
+    out = torch.zeros(3 * 301, dtype=torch.float64, device=g.dev)
+    il = torch.arange(301, dtype=torch.int32, device=g.dev)
+    for n in (0, 301):
+        rc = _lib.nbody_force_jerk(g.ctx, il.data_ptr(), n, 2.0 ** -5, out.data_ptr(),
+                                   out.data_ptr(), 0)
+        assert rc == _lib.NBODY_EINVAL, n
+        rc = _lib.nbody_correct(g.ctx, il.data_ptr(), n, 2.0 ** -5, out.data_ptr(),
+                                out.data_ptr())
+        assert rc == _lib.NBODY_EINVAL, n
+    g.sync()
+    for b, a in zip(before, (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)):
+        assert torch.equal(a, b)
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
 def test_unsoftened_unequal_masses(prec):
     # eps = 0 (self pair skipped) together with a mass spectrum (per-pair near
     # test in the mixed form)
