@@ -115,11 +115,12 @@ def test_headline_workload_sweep_and_block_steps(prec):
     g.close()
 
 
-def test_million_particle_blocks_sampled():
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_million_particle_blocks_sampled(prec):
     N, eps = 1 << 20, 1 / 4096
-    note(f"Plummer N={N} mixed, force-only blocks")
+    note(f"Plummer N={N} prec={prec}, force-only blocks")
     x, v, m = plummer(N, 1005)
-    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=NBODY_PREC_MIXED)
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
     g.init()
     for p in (65536, 4096, 128, 16, 1):
         g.autotune(p)
@@ -144,7 +145,7 @@ def test_million_particle_blocks_sampled():
         ea = relerr(acc.T.cpu().numpy()[slots], ra).max()
         ej = relerr(jerk.T.cpu().numpy()[slots], rj).max()
         note(f"  {what}: {len(slots)} checked, max rel err acc {ea:.2e} jerk {ej:.2e}")
-        assert ea <= 1e-6 and ej <= 1e-5
+        assert ea <= TOL_A[prec] and ej <= TOL_J[prec]
     g.close()
 
 
