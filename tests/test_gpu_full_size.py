@@ -5,13 +5,14 @@ particles against all N, and properties that hold at any size.
 
   Plummer N = 196608, eps = 1/1024, seed 1003 (the headline workload);
   Plummer N = 2^20, eps = 1/4096, seed 1005 (force-only blocks);
-  256 clusters of 256-8192 particles, eps = 1/256, seed 1004 (the ensemble).
+  256 clusters of 256-8192 particles, eps = 1/256, seed 1004 (the ensemble);
+  Plummer N = 196608 with Salpeter masses 0.1-100, eps = 1/1024, seed 1017.
 """
 import numpy as np
 import pytest
 
 import oracle
-from nbody_inputs import ensemble, plummer
+from nbody_inputs import ensemble, plummer, plummer_salpeter
 from paper_0709_4552_amd import NBODY_PREC_FP64, NBODY_PREC_MIXED, NBody
 
 pytestmark = pytest.mark.gpu
@@ -146,6 +147,28 @@ def test_million_particle_blocks_sampled(prec):
         ej = relerr(jerk.T.cpu().numpy()[slots], rj).max()
         note(f"  {what}: {len(slots)} checked, max rel err acc {ea:.2e} jerk {ej:.2e}")
         assert ea <= TOL_A[prec] and ej <= TOL_J[prec]
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_salpeter_full_size_sampled(prec):
+    # the benchmark's unequal-mass workload: the t = 0 sweep on the 256 most
+    # massive, the 256 most central and 256 random particles, held to the
+    # equal-mass bars
+    N, eps = 196608, 1 / 1024
+    note(f"Salpeter N={N} prec={prec}, t = 0 sweep")
+    x, v, m = plummer_salpeter(N, 1017)
+    g = NBody(x, v, m, eps, dt_min_log2=-20, dt_max_log2=-3, precision=prec)
+    g.init()
+    for p in PROBES:
+        g.autotune(p)
+    _, _, a0, j0, _, _ = g.host_state()
+    heavy = np.argsort(m)[::-1][:256]
+    idx = np.unique(np.concatenate([heavy, sample(x, 256, 256, 5)])).astype(np.int32)
+    ra, rj, _ = oracle.force(x, v, m, eps, idx)
+    ea, ej = relerr(a0[idx], ra).max(), relerr(j0[idx], rj).max()
+    note(f"  {idx.size} particles: max rel err acc {ea:.2e} jerk {ej:.2e}")
+    assert ea <= TOL_A[prec] and ej <= TOL_J[prec]
     g.close()
 
 
