@@ -189,7 +189,6 @@ def test_every_launch_shape_matches_oracle(prec, kind):
     for n in (1, 5, 40, 300, N):
         il = np.arange(N, dtype=np.int32) if n == N else rng.integers(0, N, n).astype(np.int32)
         cases.append((il, oracle.force(xp, vp, m, eps, il)))
-    scale = 10.0 if kind == "eps0" else 1.0
     jtol = TOL[prec]["j"]
     for ipl, jl in SHAPES:
         for c in range(5):
@@ -200,9 +199,9 @@ def test_every_launch_shape_matches_oracle(prec, kind):
             ea = relerr(acc.T.cpu().numpy(), ra).max()
             ej = relerr(jerk.T.cpu().numpy(), rj).max()
             ep = relerr(pot.cpu().numpy(), rp).max()
-            assert ea <= scale * TOL[prec]["a"], (ipl, jl, len(il), ea)
-            assert ej <= scale * jtol, (ipl, jl, len(il), ej)
-            assert ep <= scale * TOL[prec]["p"], (ipl, jl, len(il), ep)
+            assert ea <= TOL[prec]["a"], (ipl, jl, len(il), ea)
+            assert ej <= jtol, (ipl, jl, len(il), ej)
+            assert ep <= TOL[prec]["p"], (ipl, jl, len(il), ep)
     g.close()
 
 
