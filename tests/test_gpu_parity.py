@@ -629,6 +629,50 @@ def test_ensemble_matches_independent_oracles(prec):
 
 
 @pytest.mark.parametrize("prec", PREC, ids=PID)
+def test_ensemble_clusters_of_different_mass_scales(prec):
+    # the mixed form sizes each cluster's near field from that cluster's own
+    # mass range and speed: Salpeter spectra, equal masses and a cluster a
+    # thousand times lighter (velocities scaled to keep it in virial
+    # equilibrium) stepped together, each against its own oracle
+    note(f"ensemble of mass scales prec={prec}")
+    parts = [plummer_salpeter(600, 2201), plummer(500, 2202), plummer_salpeter(400, 2203),
+             plummer(300, 2204)]
+    x3, v3, m3 = parts[3]
+    parts[3] = (x3, v3 * np.sqrt(1e-3), m3 * 1e-3)
+    x = np.concatenate([q[0] for q in parts])
+    v = np.concatenate([q[1] for q in parts])
+    m = np.concatenate([q[2] for q in parts])
+    offs = np.concatenate([[0], np.cumsum([len(q[2]) for q in parts])]).astype(np.int64)
+    eps, T = 1 / 256, 1 / 16
+    kw = dict(dt_min_log2=-20, dt_max_log2=-4)
+    prm = oracle.params(eps, **kw)
+    g = NBody(x, v, m, eps, precision=prec, cluster_offset=offs, **kw)
+    g.init()
+    _, _, a0, j0, _, _ = g.host_state()
+    for k in range(len(parts)):
+        sl = slice(offs[k], offs[k + 1])
+        il = np.arange(offs[k + 1] - offs[k], dtype=np.int32)
+        ra, rj, _ = oracle.force(x[sl], v[sl], m[sl], eps, il)
+        ea, ej = relerr(a0[sl], ra).max(), relerr(j0[sl], rj).max()
+        note(f"  cluster {k}: start-up sweep acc {ea:.2e} jerk {ej:.2e}")
+        assert ea <= TOL[prec]["a"] and ej <= TOL[prec]["j"], k
+    g.run_until(T)
+    xg, vg, _, _, tg, _ = g.host_state()
+    assert np.all(tg == T)
+    for k in range(len(parts)):
+        sl = slice(offs[k], offs[k + 1])
+        ref = oracle.System(x[sl], v[sl], m[sl], prm)
+        E0 = sum(ref.energy())
+        ref.run(T)
+        if prec == NBODY_PREC_FP64:
+            assert np.abs(xg[sl] - ref.x).max() <= 1e-10, k
+        E1 = sum(oracle.energy(xg[sl], vg[sl], m[sl], eps))
+        note(f"  cluster {k}: dE/E {abs(E1 - E0) / abs(E0):.1e}")
+        assert abs(E1 - E0) / abs(E0) <= 1e-5, k
+    g.close()
+
+
+@pytest.mark.parametrize("prec", PREC, ids=PID)
 def test_tiny_clusters_and_ragged_sizes(prec):
     # clusters of 1, 2, 3 and 5 particles beside ragged larger ones (sizes not
     # multiples of 256): a lone particle moves in a straight line, the rest
