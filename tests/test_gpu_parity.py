@@ -731,6 +731,29 @@ def test_tiny_single_cluster_systems(prec):
         g.close()
 
 
+def test_explicit_calls_refused_on_ensembles():
+    # predict / force_jerk / correct act on one cluster's particles; on a
+    # context of several clusters they return EUNSUPPORTED and change nothing
+    note("explicit calls on an ensemble context")
+    import torch
+    x, v, m, offs = ensemble(3, 78, 100, 200)
+    g = NBody(x, v, m, 1 / 256, dt_min_log2=-20, dt_max_log2=-4, precision=NBODY_PREC_MIXED,
+              cluster_offset=offs)
+    g.init()
+    before = [q.clone() for q in (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)]
+    out = torch.zeros(3 * 4, dtype=torch.float64, device=g.dev)
+    il = torch.arange(4, dtype=torch.int32, device=g.dev)
+    assert _lib.nbody_predict(g.ctx, 0.0) == _lib.NBODY_EUNSUPPORTED
+    assert _lib.nbody_force_jerk(g.ctx, il.data_ptr(), 4, 0.0, out.data_ptr(), out.data_ptr(),
+                                 0) == _lib.NBODY_EUNSUPPORTED
+    assert _lib.nbody_correct(g.ctx, il.data_ptr(), 4, 0.0, out.data_ptr(),
+                              out.data_ptr()) == _lib.NBODY_EUNSUPPORTED
+    g.sync()
+    for b, a in zip(before, (g.pos, g.vel, g.acc, g.jerk, g.t_tick, g.level)):
+        assert torch.equal(a, b)
+    g.close()
+
+
 def test_empty_and_oversized_lists_and_no_op_run():
     # 1 <= n <= n_total for the explicit calls (EINVAL otherwise, nothing
     # enqueued); run_until to the current time steps nothing
