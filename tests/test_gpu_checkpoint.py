@@ -9,7 +9,7 @@ import os
 import numpy as np
 import pytest
 
-from nbody_inputs import ensemble, plummer
+from nbody_inputs import ensemble, plummer, plummer_salpeter
 from paper_0709_4552_amd import NBODY_PREC_FP64, NBODY_PREC_MIXED, NBody, NBodyError
 from paper_0709_4552_amd import _lib
 
@@ -31,14 +31,21 @@ def _system(kind):
         for k in range(6):
             x[offs[k]:offs[k + 1]] += [1000.0 * (k - 2), -700.0 * k, 64.0 * k + 5]
         return x, v, m, offs
+    if kind == "salpeter":
+        # a mass spectrum: the mixed form's per-pair near test, chosen from
+        # the masses at start-up, must be chosen the same way on resume
+        x, v, m = plummer_salpeter(2000, 1016)
+        return x, v, m, None
     x, v, m = plummer(2000, 1010)
     return x, v, m, None
 
 
 @pytest.mark.parametrize("kind,prec", [("single", NBODY_PREC_FP64), ("single", NBODY_PREC_MIXED),
                                        ("ensemble", NBODY_PREC_MIXED),
-                                       ("shifted", NBODY_PREC_MIXED)],
-                         ids=["single-fp64", "single-mixed", "ensemble-mixed", "shifted-mixed"])
+                                       ("shifted", NBODY_PREC_MIXED),
+                                       ("salpeter", NBODY_PREC_MIXED)],
+                         ids=["single-fp64", "single-mixed", "ensemble-mixed", "shifted-mixed",
+                              "salpeter-mixed"])
 def test_resume_is_bitwise_identical(tmp_path, kind, prec):
     note(f"checkpoint resume {kind} prec={prec}")
     x, v, m, offs = _system(kind)
